@@ -1,0 +1,400 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the passage it follows.  The oracle (two-pass, integer level
+sums, in C) is checked against: the paper's printed worked examples (golden
+fixtures), the closed forms of Table 3, an independent exact model of the
+one-pass Alg. 1 (tests/exact_ref.py), special cases with known answers, and
+Python's correctly rounded integer division.
+"""
+import itertools
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import exact_ref as X
+from oracle import oracle as O
+
+DBL = O.FMT_DOUBLE
+FLT = O.FMT_FLOAT
+
+
+def exact_state_value(states, G, L, T64, g):
+    """Exact value sum_l ((S - 1.5 ufp) + 0.25 ufp C) of one group's state,
+    decoded from the documented layout (the finalisation equation of
+    Sec. III-C without its roundings)."""
+    S, C = O.split_states(states, G, L, T64)
+    tot = Fraction(0)
+    for l in range(L):
+        s = Fraction(float(S[l, g]))
+        u = X.pow2(X.ufp_exp(s))
+        tot += (s - Fraction(3, 2) * u) + (u / 4) * int(C[l, g])
+    return tot
+
+
+def exact_sum(values):
+    """Exact sum of binary64 values as a Fraction (integer arithmetic)."""
+    v = np.asarray(values, dtype=np.float64)
+    mant, ex = np.frexp(v)
+    ints = np.ldexp(mant, 53).astype(np.int64)  # exact: 53-bit significands
+    ex = ex.astype(np.int64) - 53
+    tot = Fraction(0)
+    for e in np.unique(ex):
+        tot += Fraction(int(sum(ints[ex == e].tolist()))) * X.pow2(int(e))
+    return tot
+
+
+# ---------------------------------------------------------------- P1, P2, P3
+
+def test_p1_eft_half_precision(golden):
+    """Sec. III-B: 26.046875 and 2.8125 are 1667 and 180 times 2^-6; their sum
+    is exact in binary16."""
+    d = golden("eft_examples.txt")
+    a, b, p = float(d["half.a"]), float(d["half.b"]), int(d["half.p"])
+    assert Fraction(a) == int(d["half.alpha_a"]) * X.pow2(p)
+    assert Fraction(b) == int(d["half.alpha_b"]) * X.pow2(p)
+    assert float(np.float16(a) + np.float16(b)) == float(d["half.sum"])
+    # oracle extraction on the grid 2^p (extractor exponent p + m, m = 10)
+    E = p + 10
+    assert O.extract(a, 0, 1, 10, 1, E) == [int(d["half.alpha_a"])]
+    assert O.extract(b, 0, 1, 10, 1, E) == [int(d["half.alpha_b"])]
+    # one rounding into binary16 of the exact sum is exact
+    s = int(d["half.alpha_a"]) + int(d["half.alpha_b"])
+    assert O.round_exact(s, p, 10, -14, 15) == float(d["half.sum"])
+
+
+def test_p2_eft_toy_split(golden):
+    """Sec. III-B: q = (a (+) b) (-) a, r = b (-) q in a 4-significant-bit format."""
+    d = golden("eft_examples.txt")
+    m = int(d["toy.m"])
+    a, b = Fraction(d["toy.a"]), Fraction(d["toy.b"])
+    q = X.round_fmt(a + b, m, -20, 20) - a
+    assert q == Fraction(d["toy.q"])
+    assert b - q == Fraction(d["toy.r"])
+    # the oracle's contribution of b on the grid ulp(a) = 2^(0-m) is that q
+    (k,) = O.extract(float(b), 0, 1, m, 1, 0)
+    assert k * X.pow2(-m) == q
+
+
+def test_p3_nonassociativity_toy(golden):
+    """Sec. II-B: with m = 2 and truncation, (a+b)+c = 6 but a+(b+c) = 5."""
+    d = golden("nonassoc_toy.txt")
+    m = int(d["m"])
+    a, b, c = (Fraction(d[k]) for k in "abc")
+
+    def rd(x):
+        return X.round_fmt(x, m, -20, 20, mode="trunc")
+
+    assert rd(rd(a + b) + c) == int(d["left"])
+    assert rd(a + rd(b + c)) == int(d["right"])
+
+
+# ---------------------------------------------------------------- P4, P5
+
+@pytest.mark.parametrize("m,key", [(3, "result.m3"), (4, "result.m4")])
+def test_p4_fig2_every_order(golden, m, key):
+    """Fig. 2 (Sec. III-C): three values, W = 2, f = 4, L = 2, for all orders,
+    in the oracle and in the one-pass model."""
+    d = golden("fig2_rsum_example.txt")
+    vals = [float(x) for x in d["values"].split()]
+    W, f, L = int(d["W"]), int(d["f"]), int(d["L"])
+    B = f - (L - 1) * W  # lattice through the first extractor of a fresh state
+    for perm in itertools.permutations(vals):
+        top, K, res = O.sum_fmt(perm, (m, W, B, 30, -20, 20), L)
+        assert res == float(d[key])
+        assert X.onepass_sum(perm, m, W, f, L, -20, 20) == Fraction(d[key])
+
+
+def test_p4_literal_alg1_is_order_dependent(golden):
+    """Reading R2: Alg. 1 taken literally (ties decided by the running sum)
+    does not give one result for the Fig. 2 inputs; the state-free tie rule does."""
+    d = golden("fig2_rsum_example.txt")
+    vals = [float(x) for x in d["values"].split()]
+    lit = {X.onepass_sum(p, 3, 2, 4, 2, -20, 20, tie="literal") for p in itertools.permutations(vals)}
+    assert lit == {Fraction(x) for x in d["literal.m3.results"].split()}
+
+
+def test_p5_fig3_carry(golden):
+    """Fig. 3 (Sec. III-C): S = 27, C = 0, value 3.125 -> d = 1, S = 26."""
+    d = golden("fig3_carry.txt")
+    m, E = int(d["m"]), int(d["E"])
+    st = X.OnePassRSum(m, 2, E, 1)
+    st.S[0], st.C[0] = Fraction(int(d["S.before"])), 0
+    g = X.pow2(E - m)
+    q = X.rne_int(Fraction(d["value"]) / g) * g
+    st.S[0] += q
+    before_C = st.C[0]
+    st._carry(0)
+    assert st.C[0] - before_C == int(d["d"])
+    assert st.S[0] == int(d["S.after"]) and st.C[0] == int(d["C.after"])
+    # oracle canonical form of the same level sum: K = (27 - 24) + q/g units
+    K = int((Fraction(int(d["S.before"])) - Fraction(3, 2) * X.pow2(E)) / g + q / g)
+    S, C = O.encode(K, E, m)
+    assert S == int(d["S.after"]) and C == int(d["C.after"])
+
+
+# ---------------------------------------------------------------- P6
+
+def test_p6_sql_values_every_order(golden):
+    """Alg. 0 (Sec. I): plain sums depend on the order; repro sums do not."""
+    d = golden("sql_alg0.txt")
+    vals = [float(x) for x in d["values"].split()]
+    naive = set()
+    for p in itertools.permutations(vals):
+        acc = 0.0
+        for v in p:
+            acc += v
+        naive.add(acc)
+    assert naive == {float(x) for x in d["naive"].split()}
+    expect = {1: 1.0, 2: math.fsum(vals), 3: math.fsum(vals), 4: math.fsum(vals)}
+    for L, want in expect.items():
+        for p in itertools.permutations(vals):
+            assert O.sum_fmt(p, DBL, L)[2] == want
+            st, status = O.groupby_sum(np.zeros(3, np.int32), np.array(p), 1, L)
+            assert status == 0
+            assert O.finalize(st, 1, L)[0] == want
+
+
+# ---------------------------------------------------------------- P7
+
+def test_p7_table3_closed_forms(golden):
+    """Table 3 (Sec. VI-B): the printed bounds follow from the two formulas
+    with eps = 2^-53, W = 40, max|b| = 2 (U[1,2)) and 22 (Exp(1))."""
+    d = golden("table3_error_bounds.txt")
+    eps, W = 2.0 ** -53, 40
+    cols = [(1e3, 1.5, 2.0), (1e3, 1.0, 22.0), (1e6, 1.5, 2.0), (1e6, 1.0, 22.0)]
+    for (n, mean, mx), printed in zip(cols, d["conv"].split()):
+        assert float(f"{(n - 1) * eps * n * mean:.1e}") == float(printed)
+    for L in (1, 2, 3):
+        for (n, mean, mx), printed in zip(cols, d[f"L{L}"].split()):
+            assert float(f"{n * 2.0 ** ((1 - L) * W - 1) * mx:.1e}") == float(printed)
+
+
+@pytest.mark.parametrize("n", [1000, 10 ** 6])
+@pytest.mark.parametrize("dist", ["uniform12", "exp1"])
+@pytest.mark.parametrize("L", [1, 2, 3])
+def test_p7_error_within_bound(n, dist, L):
+    """Reading R9: |sum_l K_l g_l - sum b| <= n 2^((1-L)W) max|b| (the Table 3
+    expression without its factor 1/2, which the lattice cannot promise)."""
+    rng = np.random.default_rng([7, n, L, len(dist)])
+    v = rng.uniform(1.0, 2.0, n) if dist == "uniform12" else rng.exponential(1.0, n)
+    st, status = O.groupby_sum(np.zeros(n, np.int32), v, 1, L)
+    assert status == 0
+    err = abs(exact_state_value(st, 1, L, True, 0) - exact_sum(v))
+    bound = Fraction(n) * X.pow2((1 - L) * 40) * Fraction(float(np.max(np.abs(v))))
+    assert err <= bound
+
+
+# ---------------------------------------------------------------- P9, P10, P12
+
+@pytest.mark.parametrize("L", [2, 3, 4])
+def test_p9_integer_values_sum_exactly(L):
+    """Integer-valued doubles below 2^45 with n*max < 2^52: the second level
+    grid is below 1, so the result is the exact integer sum."""
+    rng = np.random.default_rng([9, L])
+    for trial in range(20):
+        n = int(rng.integers(1, 100))
+        ints = rng.integers(-(2 ** 45) + 1, 2 ** 45, n)
+        v = ints.astype(np.float64)
+        keys = rng.integers(0, 3, n).astype(np.int32)
+        st, _ = O.groupby_sum(keys, v, 3, L)
+        out = O.finalize(st, 3, L)
+        for g in range(3):
+            assert out[g] == float(int(ints[keys == g].sum()))
+
+
+def test_p10_exact_capture():
+    """If the last level's grid is at most the lowest set bit of every input,
+    no remainder is dropped and the level sums equal the exact sum."""
+    rng = np.random.default_rng(10)
+    for trial in range(200):
+        L = int(rng.integers(1, 5))
+        n = int(rng.integers(1, 30))
+        base = int(rng.integers(-1000, 900))
+        span = int(rng.integers(0, 30 + 40 * (L - 1)))
+        mant = rng.integers(1, 2 ** 20, n) * rng.choice([-1, 1], n)
+        ex = base + rng.integers(0, span + 1, n)
+        v = np.ldexp(mant.astype(np.float64), ex)
+        top, K, res = O.sum_fmt(v, DBL, L)
+        gL = X.pow2(-1022 + (top - (L - 1)) * 40 - 52)
+        low = min(X.pow2(int(e)) for e in ex)
+        total = sum((K[l] * X.pow2(-1022 + (top - l) * 40 - 52) for l in range(L)), Fraction(0))
+        if gL <= low:
+            assert total == exact_sum(v)
+
+
+def test_p12_special_cases():
+    rng = np.random.default_rng(12)
+    # L >= 3 and one in-domain value: the result is that value, bit for bit
+    for _ in range(2000):
+        b = float(np.ldexp(rng.standard_normal(), int(rng.integers(-1070, 1000))))
+        for L in (3, 4):
+            assert O.sum_fmt([b], DBL, L)[2] == b
+    # x and -x cancel to +0.0; an empty group is +0.0
+    for L in (1, 2, 3):
+        x = float(np.ldexp(rng.standard_normal(), int(rng.integers(-1070, 1000))))
+        r = O.sum_fmt([x, -x], DBL, L)[2]
+        assert r == 0.0 and math.copysign(1.0, r) == 1.0
+        st, _ = O.groupby_sum(np.array([0, 0], np.int32), np.array([x, -x]), 2, L)
+        out = O.finalize(st, 2, L)
+        assert np.all(out == 0.0) and not np.any(np.signbit(out))
+        assert O.sum_fmt([-0.0, -0.0], DBL, L)[2] == 0.0
+    # the smallest subnormal sums exactly
+    tiny = 5e-324
+    assert O.sum_fmt([tiny] * 7, DBL, 1)[2] == 7 * tiny
+    # L = 2 is not always exact for one value (coarse lattice): some value differs
+    diffs = 0
+    for _ in range(300):
+        b = float(np.ldexp(rng.standard_normal(), int(rng.integers(-100, 100))))
+        diffs += O.sum_fmt([b], DBL, 2)[2] != b
+    assert diffs > 0
+
+
+# ------------------------------------------------ finalisation rounding
+
+def test_round_matches_correctly_rounded_division():
+    """Reading R6: one RNE rounding with gradual underflow.  Python's
+    int / int true division is correctly rounded; compare against it."""
+    rng = np.random.default_rng(6)
+    for _ in range(5000):
+        nb = int(rng.integers(1, 120))
+        K = int(rng.integers(1, 2 ** 62)) << max(0, nb - 62)
+        K |= int(rng.integers(0, 2 ** 20))
+        K = K if rng.random() < 0.5 else -K
+        s = int(rng.integers(-1250, 900))
+        want = Fraction(K) * X.pow2(s)
+        try:
+            ref = want.numerator / want.denominator
+        except OverflowError:
+            ref = math.copysign(math.inf, K)
+        assert O.round_exact(K, s, 52, -1022, 1023) == ref
+    # ties go to even
+    assert O.round_exact(2 ** 53 + 1, 0, 52, -1022, 1023) == float(2 ** 53)
+    assert O.round_exact(2 ** 53 + 3, 0, 52, -1022, 1023) == float(2 ** 53 + 4)
+    # binary32 rounding against the exact-rational rounding of the test model
+    for _ in range(2000):
+        K = int(rng.integers(-(2 ** 62), 2 ** 62))
+        s = int(rng.integers(-230, 80))
+        ref = X.round_fmt(Fraction(K) * X.pow2(s), 23, -126, 127)
+        got = O.round_exact(K, s, 23, -126, 127)
+        assert (got == ref) if not isinstance(ref, float) else (got == ref)
+
+
+# ------------------------------------------- P11: one-pass model vs oracle
+
+def _toy_values(rng, m, n, emin_v, emax_v):
+    mant = rng.integers(2 ** m, 2 ** (m + 1), n) * rng.choice([-1, 1], n)
+    ex = rng.integers(emin_v, emax_v + 1, n)
+    v = [float(np.ldexp(float(a), int(e) - m)) for a, e in zip(mant, ex)]
+    return v
+
+
+def test_p11_toy_formats_match_onepass_model():
+    """Every order of tiny inputs in toy formats: the oracle's two-pass form
+    equals the one-pass Alg. 1 (levels, carries and result)."""
+    rng = np.random.default_rng(11)
+    for trial in range(250):
+        m = int(rng.integers(3, 9))
+        W = int(rng.integers(1, m - 1))
+        L = int(rng.integers(1, 4))
+        B = int(rng.integers(-8, 4))
+        n = int(rng.integers(1, 5))
+        v = _toy_values(rng, m, n, B - 2, B + 3 * W + 6)
+        fmt = (m, W, B, 60, -60, 200)
+        f0 = B + (L - 1) * W
+        ref = None
+        for perm in itertools.permutations(v):
+            top, K, res = O.sum_fmt(perm, fmt, L)
+            st = X.OnePassRSum(m, W, f0, L)
+            for x in perm:
+                st.add(x)
+            assert st.E[0] == B + top * W
+            lv = st.level_values()
+            for l in range(L):
+                assert lv[l] == K[l] * X.pow2(B + (top - l) * W - m)
+            assert st.finalize(-60, 200) == Fraction(res)
+            if ref is None:
+                ref = (top, K, res)
+            assert (top, K, res) == ref
+
+
+@pytest.mark.parametrize("T64", [True, False])
+def test_p11_ieee_states_match_onepass_model(T64):
+    """IEEE formats, wide exponent spread incl. subnormals and zeros: the
+    oracle's canonical (S, C) equals the running sums and carry counts the
+    one-pass Alg. 1 ends with, for random orders; finalised values agree."""
+    rng = np.random.default_rng([11, T64])
+    m, W, B = (52, 40, -1022) if T64 else (23, 18, -126)
+    emin, emax = (-1022, 1023) if T64 else (-126, 127)
+    for trial in range(120):
+        L = int(rng.integers(1, 5))
+        n = int(rng.integers(1, 7))
+        lo_e, hi_e = (-1074, 1000) if T64 else (-149, 119)
+        e0 = int(rng.integers(lo_e, hi_e))
+        ex = np.clip(e0 + rng.integers(-90, 90, n), lo_e, hi_e)
+        v = np.ldexp(rng.standard_normal(n), ex)
+        v[rng.random(n) < 0.15] = 0.0
+        v = v.astype(np.float64 if T64 else np.float32)
+        vals = [Fraction(float(x)) for x in v]
+        order = rng.permutation(n)
+        st_or, status = O.groupby_sum(np.zeros(n, np.int32), v[order], 1, L, T64=T64)
+        assert status == 0
+        S, C = O.split_states(st_or, 1, L, T64)
+        model = X.OnePassRSum(m, W, B + (L - 1) * W, L)
+        for i in rng.permutation(n):
+            model.add(vals[i])
+        for l in range(L):
+            assert Fraction(float(S[l, 0])) == model.S[l]
+            assert int(C[l, 0]) == model.C[l]
+        out = O.finalize(st_or, 1, L, T64)
+        assert Fraction(float(out[0])) == model.finalize(emin, emax)
+
+
+def test_merge_matches_lane_merge_model():
+    """operator+=(repro): the oracle's merge equals the one-pass model's
+    alignment + lane merge (Alg. 2's horizontal summation)."""
+    rng = np.random.default_rng(13)
+    for trial in range(150):
+        L = int(rng.integers(1, 5))
+        na, nb = int(rng.integers(0, 5)), int(rng.integers(0, 5))
+        ea, eb = int(rng.integers(-1000, 900)), int(rng.integers(-1000, 900))
+        va = np.ldexp(rng.standard_normal(na), ea + rng.integers(-60, 60, na))
+        vb = np.ldexp(rng.standard_normal(nb), eb + rng.integers(-60, 60, nb))
+        sa, _ = O.groupby_sum(np.zeros(na, np.int32), va, 1, L)
+        sb, _ = O.groupby_sum(np.zeros(nb, np.int32), vb, 1, L)
+        merged = O.merge(sa, sb, 1, L)
+        ma = X.OnePassRSum(52, 40, -1022 + (L - 1) * 40, L)
+        mb = X.OnePassRSum(52, 40, -1022 + (L - 1) * 40, L)
+        for x in va:
+            ma.add(Fraction(float(x)))
+        for x in vb:
+            mb.add(Fraction(float(x)))
+        ma.merge(mb)
+        S, C = O.split_states(merged, 1, L)
+        for l in range(L):
+            assert Fraction(float(S[l, 0])) == ma.S[l] and int(C[l, 0]) == ma.C[l]
+        # and equals the states of the concatenated rows
+        sc, _ = O.groupby_sum(np.zeros(na + nb, np.int32), np.concatenate([va, vb]), 1, L)
+        assert np.array_equal(sc, merged)
+
+
+# ------------------------------------------------------ error handling
+
+def test_error_rows_are_skipped_with_status_bits():
+    """Readings R7/R8: bad keys, NaN/Inf and out-of-domain values are skipped
+    and reported; the remaining rows give the same states as without them."""
+    keys = np.array([0, 1, 5, -1, 1, 0, 2], np.int32)
+    vals = np.array([1.5, 2.0, 3.0, 4.0, np.nan, np.inf, 2.0 ** 1005])
+    st, status = O.groupby_sum(keys, vals, 3, 2)
+    assert status == O.ERR_KEY | O.ERR_NONFINITE | O.ERR_RANGE
+    clean, s2 = O.groupby_sum(np.array([0, 1], np.int32), np.array([1.5, 2.0]), 3, 2)
+    assert s2 == 0 and np.array_equal(st, clean)
+    # largest in-domain value is accepted
+    st, status = O.groupby_sum(np.array([0], np.int32), np.array([np.nextafter(2.0 ** 1005, 0)]), 1, 2)
+    assert status == 0
+    # float accumulators: domain 2^120; f64 values into float states rejected
+    st, status = O.groupby_sum(np.array([0, 0], np.int32), np.array([2.0 ** 120, 1.0], np.float32), 1, 2, T64=False)
+    assert status == O.ERR_RANGE
+    with pytest.raises(RuntimeError):
+        O.groupby_sum(np.array([0], np.int32), np.array([1.0]), 1, 2, T64=False)
