@@ -1,0 +1,153 @@
+/*
+ * repro.h -- C interface of librepro: reproducible GroupBy-SUM over
+ * floating-point columns into the accumulator type repro<T,L> on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: Mueller, Arteaga, Hoefler, Alonso, "Reproducible Floating-Point
+ * Aggregation in RDBMSs" (arXiv 1802.09883).  The problem statement is
+ * Sec. II-A (GroupBy turns <key,value> pairs into <key,aggregate> pairs; the
+ * aggregate must have the same bits for every execution); the accumulator is
+ * the repro<ScalarT,L> type of Sec. IV, built on RSum (Sec. III-C, Alg. 1)
+ * with its operator+=(ScalarT), operator+=(repro), resumable state and the
+ * finalisation equation of Sec. III-C.
+ *
+ * Conventions for every entry point:
+ *   - All buffers are DEVICE pointers owned by the caller.  The library
+ *     allocates nothing; scratch memory is the caller's `workspace`.
+ *   - Work is enqueued asynchronously on `stream` (0 = the null stream);
+ *     results are visible after the stream is synchronised.
+ *   - Host return value: REPRO_OK, or REPRO_EINVAL for invalid arguments
+ *     (checked synchronously; nothing is enqueued), or REPRO_EHIP when a
+ *     kernel launch fails.
+ *   - Calls on different streams are independent; calls that touch the same
+ *     states or workspace must be ordered by the caller.
+ *
+ * Accumulator formats (paper: W = 18 for float, 40 for double; m = fraction
+ * bits; extractor exponents on the fixed lattice E_j = B + j*W, B = emin):
+ *   T = double: m = 52, W = 40, B = -1022, top index j in [L-1, 51],
+ *               value domain |b| < 2^1005.
+ *   T = float:  m = 23, W = 18, B = -126,  top index j in [L-1, 14],
+ *               value domain |b| < 2^120.
+ *
+ * State layout (num_groups = G), "canonical" at every call boundary:
+ *   S[l][g]  : T,       l = 0..L-1 (level 0 = first, largest level),
+ *                       S in [1.5, 1.75) * 2^E_l with E_l = E_top - l*W;
+ *   C[l][g]  : int64_t, the carry-bit counts, starting at the next
+ *                       multiple of 8 bytes after the S block.
+ * The exact value of level l is (S - 1.5*2^E_l) + 0.25*2^E_l*C (Sec. III-C).
+ * An empty group has E_top = E_{L-1} and all C = 0.  Canonical states are
+ * unique, so two states can be compared bit for bit.
+ */
+#ifndef REPRO_H
+#define REPRO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* host-side return codes */
+typedef enum { REPRO_OK = 0, REPRO_EINVAL = -1, REPRO_EHIP = -2 } repro_status_t;
+
+/* device status bits, OR-ed into the caller's status word */
+enum {
+    REPRO_ERR_KEY = 1u,       /* key outside [0, num_groups): row skipped      */
+    REPRO_ERR_NONFINITE = 2u, /* NaN or +-Inf value: row skipped              */
+    REPRO_ERR_RANGE = 4u      /* |value| beyond the domain of T: row skipped   */
+};
+
+typedef enum { REPRO_F32 = 0, REPRO_F64 = 1 } repro_scalar_t;
+typedef enum { REPRO_I32 = 0, REPRO_I64 = 1 } repro_key_t;
+
+/*
+ * Bytes of a state buffer for G groups (layout above).  Returns 0 for
+ * invalid arguments (G < 1, L outside 1..4).
+ */
+size_t repro_state_bytes(int64_t num_groups, repro_scalar_t T, int L);
+
+/*
+ * Bytes of scratch memory repro_groupby_sum needs for these sizes (may be
+ * 0).  Depends only on the arguments, never on the data.
+ */
+size_t repro_workspace_bytes(int64_t n, int64_t num_groups, repro_key_t kt, repro_scalar_t vt,
+                             repro_scalar_t T, int L);
+
+/* Writes the empty state of every group (the initialised state Alg. 1 loads). */
+int repro_state_init(void* states, int64_t num_groups, repro_scalar_t T, int L, hipStream_t stream);
+
+/*
+ * GroupBy-SUM (Sec. II-A; the repro type's operator+=(ScalarT), Sec. IV):
+ * adds rows i = 0..n-1, value values[i] into group keys[i], to `states`
+ * (accumulated into: pass freshly initialised states for a plain GroupBy,
+ * or earlier results to resume, as Alg. 1's load/store of state allows).
+ *
+ *   keys       int32 or int64 (kt), dense group ids in [0, num_groups)
+ *              (identity hashing, Sec. VI-A); others set REPRO_ERR_KEY.
+ *   values     float or double (vt).  vt = F32 with T = F64 widens exactly;
+ *              vt = F64 with T = F32 is REPRO_EINVAL.
+ *   n          rows, >= 0 (n = 0 enqueues nothing).
+ *   num_groups 1 .. 2^31-1.
+ *   L          levels, 1..4.
+ *   workspace  >= repro_workspace_bytes(...) bytes, 256-byte aligned device
+ *              memory (may be NULL if that size is 0); contents on entry are
+ *              ignored.
+ *   status     device uint32, OR-ed with REPRO_ERR_* bits; may be NULL.
+ *
+ * Result bits depend only on the multiset of (key, value) rows deposited
+ * into each group since initialisation: not on the row order, the split
+ * into calls, the stream or the launch configuration.  Groups that saw a
+ * skipped row hold the sum of their other rows.
+ */
+int repro_groupby_sum(const void* keys, repro_key_t kt, const void* values, repro_scalar_t vt, int64_t n,
+                      int64_t num_groups, repro_scalar_t T, int L, void* states, void* workspace,
+                      size_t workspace_bytes, uint32_t* status, hipStream_t stream);
+
+/*
+ * dst[g] += src[g] for every group (operator+=(repro), Sec. IV; the merge
+ * phase of Alg. 3, Sec. V-B): the larger top wins, the other state's levels
+ * move down by the difference (its lowest levels drop off), level sums add
+ * exactly, carries renormalise.  dst and src may not overlap.
+ */
+int repro_merge(void* dst, const void* src, int64_t num_groups, repro_scalar_t T, int L, hipStream_t stream);
+
+/*
+ * out[g] = the finalised sum of group g, type T (equation of Sec. III-C):
+ * each level's exact value is rounded once to T, then the levels are added
+ * in T from the last one to the first.  Empty groups give +0.0.
+ */
+int repro_finalize(const void* states, int64_t num_groups, repro_scalar_t T, int L, void* out,
+                   hipStream_t stream);
+
+/*
+ * Baseline, NOT reproducible: out[g] += values[i] for keys[i] == g with
+ * plain double-precision atomic adds (the built-in floating-point SUM the
+ * paper compares against, Sec. VI).  out is double[num_groups], accumulated
+ * into; status as above (bad keys and non-finite values are skipped).
+ */
+int repro_plain_groupby_sum(const void* keys, repro_key_t kt, const void* values, repro_scalar_t vt, int64_t n,
+                            int64_t num_groups, double* out, uint32_t* status, hipStream_t stream);
+
+/*
+ * Profiling aid.  repro_profile_arm(k) makes the next k repro_groupby_sum
+ * calls issued by the calling host thread record a pair of HIP events on
+ * their stream, right before and right after the aggregation kernel (the
+ * one pass over the rows).  repro_profile_read(ms, cap, &count) waits for
+ * the recorded events and writes the elapsed milliseconds of each measured
+ * launch, in call order (at most cap), then disarms.  k <= 4096.  Events are
+ * created on first use, per thread; no device memory is involved.
+ */
+int repro_profile_arm(int max_launches);
+int repro_profile_read(float* ms, int cap, int* count);
+
+/* Library version string. */
+const char* repro_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REPRO_H */

@@ -1,0 +1,65 @@
+"""ctypes loader for librepro.so (the HIP library); marshalling only.
+
+The library must have been built (``__graft_entry__.build()``); there is no
+fallback: a missing or unloadable library raises at first use.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librepro.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "repro.h")
+
+REPRO_OK, REPRO_EINVAL, REPRO_EHIP = 0, -1, -2
+ERR_KEY, ERR_NONFINITE, ERR_RANGE = 1, 2, 4
+F32, F64 = 0, 1
+I32, I64 = 0, 1
+
+_lib = None
+
+
+def header_functions():
+    """Names of the functions declared in include/repro.h."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    return re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(repro_[a-z_0-9]+)\s*\(", text, re.M)
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
+    lib.repro_state_bytes.restype = sz
+    lib.repro_state_bytes.argtypes = [i64, i32, i32]
+    lib.repro_workspace_bytes.restype = sz
+    lib.repro_workspace_bytes.argtypes = [i64, i64, i32, i32, i32, i32]
+    lib.repro_state_init.argtypes = [vp, i64, i32, i32, vp]
+    lib.repro_groupby_sum.argtypes = [vp, i32, vp, i32, i64, i64, i32, i32, vp, vp, sz, vp, vp]
+    lib.repro_merge.argtypes = [vp, vp, i64, i32, i32, vp]
+    lib.repro_finalize.argtypes = [vp, i64, i32, i32, vp, vp]
+    lib.repro_plain_groupby_sum.argtypes = [vp, i32, vp, i32, i64, i64, vp, vp, vp]
+    lib.repro_profile_arm.argtypes = [i32]
+    lib.repro_profile_arm.restype = ctypes.c_int
+    lib.repro_profile_read.argtypes = [vp, i32, vp]
+    lib.repro_profile_read.restype = ctypes.c_int
+    lib.repro_version.restype = ctypes.c_char_p
+    lib.repro_version.argtypes = []
+    for name in ("repro_state_init", "repro_groupby_sum", "repro_merge", "repro_finalize",
+                 "repro_plain_groupby_sum"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def check(rc: int, what: str):
+    if rc == REPRO_EINVAL:
+        raise ValueError(f"{what}: invalid argument")
+    if rc != REPRO_OK:
+        raise RuntimeError(f"{what}: HIP error (code {rc})")

@@ -1,0 +1,154 @@
+"""Python front end of librepro: reproducible GroupBy-SUM into repro<T,L>.
+
+Thin wrappers over the C interface in include/repro.h: PyTorch tensors carry
+device memory and streams; every step of the computation runs in the HIP
+kernels of librepro.so.  Paper: Mueller, Arteaga, Hoefler, Alonso,
+"Reproducible Floating-Point Aggregation in RDBMSs" (arXiv 1802.09883);
+RSum(expression, L) of Sec. V-D is ``groupby_sum`` + ``finalize``.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+_SCALAR = {torch.float32: _lib.F32, torch.float64: _lib.F64}
+_KEY = {torch.int32: _lib.I32, torch.int64: _lib.I64}
+
+
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(device, stream):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _T(T):
+    if T not in _SCALAR:
+        raise TypeError("T must be torch.float32 or torch.float64")
+    return _SCALAR[T]
+
+
+def state_bytes(num_groups: int, L: int = 2, T=torch.float64) -> int:
+    return int(_lib.load().repro_state_bytes(num_groups, _T(T), L))
+
+
+def workspace_bytes(n: int, num_groups: int, key_dtype=torch.int32, value_dtype=torch.float64,
+                    L: int = 2, T=torch.float64) -> int:
+    return int(_lib.load().repro_workspace_bytes(n, num_groups, _KEY[key_dtype], _SCALAR[value_dtype], _T(T), L))
+
+
+def split_states(states: torch.Tensor, num_groups: int, L: int = 2, T=torch.float64):
+    """Views (S[L, G] of dtype T, C[L, G] int64) of a state buffer."""
+    es = 8 if T == torch.float64 else 4
+    sb = (num_groups * L * es + 7) // 8 * 8
+    S = states[: num_groups * L * es].view(T).view(L, num_groups)
+    C = states[sb: sb + num_groups * L * 8].view(torch.int64).view(L, num_groups)
+    return S, C
+
+
+def state_init(num_groups: int, L: int = 2, T=torch.float64, device="cuda", stream=None) -> torch.Tensor:
+    lib = _lib.load()
+    st = torch.empty(state_bytes(num_groups, L, T), dtype=torch.uint8, device=device)
+    _lib.check(lib.repro_state_init(_vp(st), num_groups, _T(T), L, _stream(st.device, stream)), "state_init")
+    return st
+
+
+_WS = {}
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    key = torch.device(device)
+    ws = _WS.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _WS[key] = ws
+    return ws
+
+
+def groupby_sum(keys: torch.Tensor, values: torch.Tensor, num_groups: int, L: int = 2, T=torch.float64,
+                states: torch.Tensor | None = None, status: torch.Tensor | None = None,
+                workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Accumulate rows (keys[i], values[i]) into repro<T,L> states per group.
+
+    Returns ``states`` (a fresh state buffer if none is given).  ``status`` is
+    an optional device uint32 tensor OR-ed with REPRO_ERR_* bits."""
+    lib = _lib.load()
+    if keys.dtype not in _KEY or values.dtype not in _SCALAR:
+        raise TypeError("keys int32/int64, values float32/float64")
+    if keys.shape != values.shape or keys.dim() != 1:
+        raise ValueError("keys and values must be 1-D of equal length")
+    if not (keys.is_cuda and values.is_cuda) or keys.device != values.device:
+        raise ValueError("keys and values must be on the same GPU")
+    keys, values = keys.contiguous(), values.contiguous()
+    dev = keys.device
+    if states is None:
+        states = state_init(num_groups, L, T, dev, stream)
+    n = keys.numel()
+    need = workspace_bytes(n, num_groups, keys.dtype, values.dtype, L, T)
+    ws = workspace if workspace is not None else (_workspace(need, dev) if need else None)
+    rc = lib.repro_groupby_sum(_vp(keys), _KEY[keys.dtype], _vp(values), _SCALAR[values.dtype], n, num_groups,
+                               _T(T), L, _vp(states), _vp(ws), ws.numel() if ws is not None else 0, _vp(status),
+                               _stream(dev, stream))
+    _lib.check(rc, "groupby_sum")
+    return states
+
+
+def merge(dst: torch.Tensor, src: torch.Tensor, num_groups: int, L: int = 2, T=torch.float64, stream=None):
+    """dst += src group by group (operator+=(repro)); returns dst."""
+    lib = _lib.load()
+    _lib.check(lib.repro_merge(_vp(dst), _vp(src), num_groups, _T(T), L, _stream(dst.device, stream)), "merge")
+    return dst
+
+
+def finalize(states: torch.Tensor, num_groups: int, L: int = 2, T=torch.float64, out=None, stream=None):
+    """Finalised sums (type T) of every group."""
+    lib = _lib.load()
+    if out is None:
+        out = torch.empty(num_groups, dtype=T, device=states.device)
+    _lib.check(lib.repro_finalize(_vp(states), num_groups, _T(T), L, _vp(out), _stream(states.device, stream)),
+               "finalize")
+    return out
+
+
+def plain_groupby_sum(keys: torch.Tensor, values: torch.Tensor, num_groups: int, out=None, status=None,
+                      stream=None) -> torch.Tensor:
+    """Non-reproducible baseline: double-precision atomic GroupBy-SUM."""
+    lib = _lib.load()
+    keys, values = keys.contiguous(), values.contiguous()
+    if out is None:
+        out = torch.zeros(num_groups, dtype=torch.float64, device=keys.device)
+    rc = lib.repro_plain_groupby_sum(_vp(keys), _KEY[keys.dtype], _vp(values), _SCALAR[values.dtype], keys.numel(),
+                                     num_groups, _vp(out), _vp(status), _stream(keys.device, stream))
+    _lib.check(rc, "plain_groupby_sum")
+    return out
+
+
+def rsum(keys, values, num_groups: int, L: int = 2, T=torch.float64, stream=None):
+    """RSum(expression, L): GroupBy-SUM and finalisation in one call."""
+    st = groupby_sum(keys, values, num_groups, L, T, stream=stream)
+    return finalize(st, num_groups, L, T, stream=stream)
+
+
+def profile_arm(max_launches: int = 1):
+    """Time the aggregation kernels of this thread's next groupby_sum calls."""
+    _lib.check(_lib.load().repro_profile_arm(max_launches), "profile_arm")
+
+
+def profile_read(cap: int = 4096):
+    """Milliseconds of each armed aggregation kernel, in call order."""
+    ms = (ctypes.c_float * cap)()
+    cnt = ctypes.c_int(0)
+    _lib.check(_lib.load().repro_profile_read(ms, cap, ctypes.byref(cnt)), "profile_read")
+    return [float(ms[i]) for i in range(cnt.value)]
+
+
+def state_reset(states: torch.Tensor, num_groups: int, L: int = 2, T=torch.float64, stream=None):
+    """Re-initialise an existing state buffer in place (empty groups)."""
+    _lib.check(_lib.load().repro_state_init(_vp(states), num_groups, _T(T), L, _stream(states.device, stream)),
+               "state_init")
+    return states

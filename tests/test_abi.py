@@ -1,0 +1,58 @@
+"""The C interface library loads and exports what include/repro.h declares;
+host-side argument checks behave as documented (no GPU work is issued)."""
+import ctypes
+import os
+
+import pytest
+
+from paper_1802_09883_amd import _lib
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1802_09883_amd import build
+        build.build()
+    return _lib.load()
+
+
+def test_exports_every_declared_function(lib):
+    names = _lib.header_functions()
+    assert set(names) >= {"repro_state_bytes", "repro_workspace_bytes", "repro_state_init", "repro_groupby_sum",
+                          "repro_merge", "repro_finalize", "repro_plain_groupby_sum", "repro_version"}
+    for name in names:
+        assert hasattr(lib, name), name
+    assert b"gfx950" in lib.repro_version()
+
+
+def test_state_bytes_layout(lib):
+    # S block (padded to 8 bytes) + int64 C block
+    assert lib.repro_state_bytes(16, _lib.F64, 2) == 16 * 2 * 8 + 16 * 2 * 8
+    assert lib.repro_state_bytes(3, _lib.F32, 1) == 16 + 3 * 8
+    assert lib.repro_state_bytes(0, _lib.F64, 2) == 0
+    assert lib.repro_state_bytes(4, _lib.F64, 5) == 0
+
+
+def test_workspace_depends_on_sizes_only(lib):
+    a = lib.repro_workspace_bytes(10 ** 6, 16, _lib.I32, _lib.F64, _lib.F64, 2)
+    b = lib.repro_workspace_bytes(10 ** 6, 16, _lib.I64, _lib.F32, _lib.F64, 2)
+    assert a == b > 0
+    assert lib.repro_workspace_bytes(10 ** 6, 16, _lib.I32, _lib.F64, _lib.F64, 0) == 0
+
+
+def test_invalid_arguments_return_einval_without_gpu(lib):
+    p = ctypes.c_void_p(0x1000)  # never dereferenced: checks fail first
+    null = ctypes.c_void_p(0)
+    # float64 values into float accumulators
+    assert lib.repro_groupby_sum(p, 0, p, _lib.F64, 10, 4, _lib.F32, 2, p, p, 1 << 30, null, null) == _lib.REPRO_EINVAL
+    # L out of range, no groups, negative n, missing states
+    assert lib.repro_groupby_sum(p, 0, p, 1, 10, 4, 1, 5, p, p, 1 << 30, null, null) == _lib.REPRO_EINVAL
+    assert lib.repro_groupby_sum(p, 0, p, 1, 10, 0, 1, 2, p, p, 1 << 30, null, null) == _lib.REPRO_EINVAL
+    assert lib.repro_groupby_sum(p, 0, p, 1, -1, 4, 1, 2, p, p, 1 << 30, null, null) == _lib.REPRO_EINVAL
+    assert lib.repro_groupby_sum(p, 0, p, 1, 10, 4, 1, 2, null, p, 1 << 30, null, null) == _lib.REPRO_EINVAL
+    # workspace too small
+    assert lib.repro_groupby_sum(p, 0, p, 1, 10 ** 6, 16, 1, 2, p, p, 16, null, null) == _lib.REPRO_EINVAL
+    # n = 0 is a no-op
+    assert lib.repro_groupby_sum(null, 0, null, 1, 0, 4, 1, 2, p, null, 0, null, null) == _lib.REPRO_OK
+    assert lib.repro_merge(p, p, 4, 1, 2, null) == _lib.REPRO_EINVAL
+    assert lib.repro_finalize(p, 4, 1, 2, null, null) == _lib.REPRO_EINVAL

@@ -1,0 +1,250 @@
+"""Bit-exact parity of the HIP library with the CPU oracle (needs a GPU).
+
+Every comparison is on whole state buffers (canonical S and C bits) and on
+finalised sums, element by element, with tolerance 0: the method is exact,
+so any difference is a bug.  Inputs are seeded and synthetic (see
+paper_1802_09883_amd.workloads).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1802_09883_amd import workloads as WL
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1802_09883_amd import api
+else:  # collected on CPU-only hosts, never run there
+    api = None
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def TT(T64):
+    return torch.float64 if T64 else torch.float32
+
+
+def gpu_groupby(keys, vals, G, L, T64=True, states=None, keys_t=None, vals_t=None):
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    st = api.groupby_sum(dev(keys) if keys_t is None else keys_t, dev(vals) if vals_t is None else vals_t, G, L,
+                         TT(T64), states=states, status=status)
+    torch.cuda.synchronize()
+    return st, int(status.item())
+
+
+def assert_same_states(gpu_st, orc_st, G, L, T64, what=""):
+    a = gpu_st.cpu().numpy()
+    Sg, Cg = O.split_states(a, G, L, T64)
+    So, Co = O.split_states(orc_st, G, L, T64)
+    if np.array_equal(Sg.view(np.uint8), So.view(np.uint8)) and np.array_equal(Cg, Co):
+        return
+    bad = np.nonzero(np.any((Sg != So) | (Cg != Co), axis=0))[0]
+    g = int(bad[0])
+    raise AssertionError(f"{what}: {len(bad)} groups differ, first g={g}: gpu S={Sg[:, g]!r} C={Cg[:, g]!r} "
+                         f"oracle S={So[:, g]!r} C={Co[:, g]!r}")
+
+
+def check_case(keys, vals, G, L, T64=True, what=""):
+    say(f"case {what}: n={len(keys)} G={G} L={L} T64={T64} kt={keys.dtype} vt={vals.dtype}")
+    orc, ost = O.groupby_sum(keys, vals, G, L, T64, threads=8)
+    st, status = gpu_groupby(keys, vals, G, L, T64)
+    assert status == ost, f"{what}: status {status} vs oracle {ost}"
+    assert_same_states(st, orc, G, L, T64, what)
+    out = api.finalize(st, G, L, TT(T64))
+    torch.cuda.synchronize()
+    ref = O.finalize(orc, G, L, T64)
+    assert np.array_equal(out.cpu().numpy().view(np.uint8), ref.view(np.uint8)), f"{what}: finalize differs"
+    return st
+
+
+# ------------------------------------------------------------ configs
+
+def test_plain_config_full():
+    keys, vals = WL.plain()
+    check_case(keys, vals, 16, 2, True, "plain 1M x 16 groups, repro<double,2>")
+
+
+def test_lowcard_config_reduced():
+    keys, v64, v32 = WL.lowcard(n=3_000_001)
+    check_case(keys, v64, 1024, 3, True, "lowcard f64, repro<double,3>")
+    check_case(keys, v32, 1024, 3, True, "lowcard f32 -> repro<double,3>")
+
+
+def test_lowcard_config_full():
+    keys, v64, v32 = WL.lowcard()
+    kt = dev(keys)
+    for name, vals in (("f64", v64), ("f32", v32)):
+        say(f"case lowcard full {name}")
+        orc, ost = O.groupby_sum(keys, vals, 1024, 3, True, threads=16)
+        st, status = gpu_groupby(keys, vals, 1024, 3, True, keys_t=kt)
+        assert status == ost == 0
+        assert_same_states(st, orc, 1024, 3, True, f"lowcard full {name}")
+        out = api.finalize(st, 1024, 3).cpu().numpy()
+        assert np.array_equal(out, O.finalize(orc, 1024, 3))
+
+
+# ------------------------------------------------------- shapes, types
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4])
+@pytest.mark.parametrize("kdt", [np.int32, np.int64])
+@pytest.mark.parametrize("n", [1, 5, 2047, 2048, 2049, 100_003])
+def test_shapes_and_levels(L, kdt, n):
+    rng = np.random.default_rng([L, n, np.dtype(kdt).itemsize])
+    G = int(rng.choice([1, 7, 16, 100, 1024]))
+    keys = rng.integers(0, G, n).astype(kdt)
+    vals = np.ldexp(rng.standard_normal(n), rng.integers(-200, 200, n))
+    check_case(keys, vals, G, L, True, "shapes f64")
+    check_case(keys, vals.astype(np.float32), G, L, False, "shapes f32 acc")
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4])
+def test_largest_lds_group_count(L):
+    G = {1: 4096, 2: 2730, 3: 2048, 4: 1638}[L]
+    rng = np.random.default_rng(L)
+    n = 300_000
+    keys = rng.integers(0, G, n).astype(np.int32)
+    vals = np.ldexp(rng.standard_normal(n), rng.integers(-40, 40, n))
+    check_case(keys, vals, G, L, True, "largest LDS G")
+
+
+def test_misaligned_columns_take_scalar_loads():
+    keys, vals = WL.plain(n=50_001, salt=3)
+    kt, vt = dev(keys), dev(vals)
+    st, status = gpu_groupby(None, None, 16, 2, keys_t=kt[1:], vals_t=vt[1:])
+    orc, _ = O.groupby_sum(keys[1:], vals[1:], 16, 2)
+    assert status == 0
+    assert_same_states(st, orc, 16, 2, True, "misaligned")
+
+
+def test_extreme_values():
+    rng = np.random.default_rng(77)
+    n = 200_000
+    parts = [
+        np.ldexp(rng.standard_normal(n // 5), rng.integers(-1074, -1000, n // 5)),  # subnormal / tiny
+        np.ldexp(rng.standard_normal(n // 5), rng.integers(900, 1004, n // 5)),     # near the domain edge
+        np.ldexp(np.ones(n // 5), rng.integers(-1074, 1004, n // 5)),               # powers of two
+        np.zeros(n // 10), -np.zeros(n // 10),
+        np.ldexp(rng.integers(-(2 ** 39), 2 ** 39, n // 5).astype(np.float64) + 0.5, -10),  # halves: ties
+    ]
+    vals = np.concatenate(parts)
+    keys = rng.integers(0, 9, len(vals)).astype(np.int32)
+    for L in (1, 2, 3, 4):
+        check_case(keys, vals, 9, L, True, "extreme f64")
+    v32 = np.concatenate([np.ldexp(rng.standard_normal(n), rng.integers(-149, 119, n)).astype(np.float32),
+                          np.zeros(1000, np.float32)])
+    k32 = rng.integers(0, 5, len(v32)).astype(np.int32)
+    for L in (1, 2, 3, 4):
+        check_case(k32, v32, 5, L, False, "extreme f32 acc")
+        check_case(k32, v32, 5, L, True, "extreme f32 -> double")
+
+
+def test_single_group_many_rows_carry():
+    """Carry stress: one group, large units at every level, many workgroups."""
+    rng = np.random.default_rng(5)
+    n = 6_000_000
+    vals = np.ldexp(1.0 + rng.random(n), 40)  # all near one binade: units near 2^39
+    keys = np.zeros(n, np.int32)
+    check_case(keys, vals, 1, 3, True, "carry stress")
+    check_case(keys, -vals, 1, 2, True, "carry stress negative")
+
+
+def test_error_rows_status_and_skip():
+    keys = np.array([0, 1, 5, -1, 1, 0, 2, 3] * 1000, np.int32)
+    vals = np.array([1.5, 2.0, 3.0, 4.0, np.nan, np.inf, 2.0 ** 1005, -np.inf] * 1000)
+    st = check_case(keys, vals, 4, 2, True, "error rows")
+    v32 = np.array([1.0, 2.0 ** 121, np.nan, 3.0] * 100, np.float32)
+    k32 = np.array([0, 0, 1, 7] * 100, np.int32)
+    check_case(k32, v32, 2, 2, False, "error rows f32")
+
+
+# ------------------------------------------- schedule / resume / merge
+
+def test_chunked_calls_and_host_roundtrip_resume():
+    keys, v64, _ = WL.lowcard(n=1_000_000, salt=9, with_f32=False)
+    orc, _ = O.groupby_sum(keys, v64, 1024, 3)
+    st = api.state_init(1024, 3)
+    cuts = [0, 1, 999, 2048 * 7 + 3, 400_000, 1_000_000]
+    kt, vt = dev(keys), dev(v64)
+    for i, (b, e) in enumerate(zip(cuts[:-1], cuts[1:])):
+        st = api.groupby_sum(kt[b:e], vt[b:e], 1024, 3, states=st)
+        if i == 2:  # checkpoint to host and restore
+            torch.cuda.synchronize()
+            st = torch.from_numpy(st.cpu().numpy().copy()).cuda()
+    torch.cuda.synchronize()
+    assert_same_states(st, orc, 1024, 3, True, "chunked resume")
+
+
+def test_permutation_invariance_on_gpu():
+    keys, v64, _ = WL.lowcard(n=500_000, salt=4, with_f32=False)
+    a, _ = gpu_groupby(keys, v64, 1024, 3)
+    p = np.random.default_rng(1).permutation(len(keys))
+    b, _ = gpu_groupby(keys[p], v64[p], 1024, 3)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("T64", [True, False])
+def test_merge_and_finalize_match_oracle(T64):
+    rng = np.random.default_rng([3, T64])
+    G = 333
+    for L in (1, 2, 3, 4):
+        ka = rng.integers(0, G, 50_000).astype(np.int64)
+        kb = rng.integers(0, G, 70_000).astype(np.int64)
+        span = (-1000, 1000) if T64 else (-140, 110)
+        va = np.ldexp(rng.standard_normal(50_000), rng.integers(*span, 50_000))
+        vb = np.ldexp(rng.standard_normal(70_000), rng.integers(*span, 70_000))
+        if not T64:
+            va, vb = va.astype(np.float32), vb.astype(np.float32)
+        oa, _ = O.groupby_sum(ka, va, G, L, T64)
+        ob, _ = O.groupby_sum(kb, vb, G, L, T64)
+        ga, gb = dev(oa), dev(ob)
+        api.merge(ga, gb, G, L, TT(T64))
+        torch.cuda.synchronize()
+        assert_same_states(ga, O.merge(oa, ob, G, L, T64), G, L, T64, "merge")
+        out = api.finalize(dev(oa), G, L, TT(T64)).cpu().numpy()
+        assert np.array_equal(out.view(np.uint8), O.finalize(oa, G, L, T64).view(np.uint8))
+
+
+def test_state_init_and_empty_input():
+    for T64 in (True, False):
+        for L in (1, 2, 3, 4):
+            st = api.state_init(37, L, TT(T64))
+            torch.cuda.synchronize()
+            assert np.array_equal(st.cpu().numpy(), O.state_init(37, T64, L))
+            before = st.clone()
+            api.groupby_sum(torch.zeros(0, dtype=torch.int32, device="cuda"),
+                            torch.zeros(0, dtype=TT(T64), device="cuda"), 37, L, TT(T64), states=st)
+            torch.cuda.synchronize()
+            assert torch.equal(st, before)
+            out = api.finalize(st, 37, L, TT(T64)).cpu().numpy()
+            assert np.all(out == 0) and not np.any(np.signbit(out))
+
+
+def test_invalid_arguments_are_rejected():
+    k = torch.zeros(4, dtype=torch.int32, device="cuda")
+    v = torch.zeros(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        api.groupby_sum(k, v, 4, 2, torch.float32)  # f64 values into float states
+    with pytest.raises(ValueError):
+        api.groupby_sum(k, v, 4, 5)  # L out of range
+    with pytest.raises(ValueError):
+        api.groupby_sum(k, v, 0, 2)  # no groups
+
+
+def test_plain_baseline_close_to_exact():
+    keys, vals = WL.plain(n=200_000, salt=2)
+    out = api.plain_groupby_sum(dev(keys), dev(vals), 16).cpu().numpy()
+    orc, _ = O.groupby_sum(keys, vals, 16, 3)
+    ref = O.finalize(orc, 16, 3)
+    scale = np.array([np.abs(vals[keys == g]).sum() for g in range(16)])
+    assert np.all(np.abs(out - ref) <= 1e-12 * scale)
