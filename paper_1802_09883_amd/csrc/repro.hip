@@ -12,15 +12,16 @@
 //                pre-rounded extraction into L integer units, exact int64
 //                adds into per-(level, group) LDS bins.  At the end the
 //                workgroup writes its partial (top, K[L]) per group.
-//   k_merge_l1   reduces blocks of partials: common top per group, shift,
-//                exact integer sums split into (hi, lo) carry form.
-//   k_merge_l2   folds the reduced partials into the caller's states and
-//                writes canonical (S, C) (carry renormalisation).
+//   k_merge_l1/l2 fold all partials into the caller's states: common top
+//                per group, shift, exact integer sums in (hi, lo) carry
+//                form, canonical (S, C) (carry renormalisation).
 // Exact integer addition is associative, so every launch shape, chunking
 // and schedule produces the same bits.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
+
+#include <algorithm>
 
 #include "repro.h"
 #include "repro_device.hpp"
@@ -29,19 +30,17 @@ using namespace repro;
 
 namespace {
 
-constexpr int AGG_BLOCK = 256;
+constexpr int AGG_BLOCK = 1024;  // 16 waves: one workgroup per CU
 constexpr int ROWS_PER_THREAD = 8;
+constexpr int PREFETCH = 1;  // tiles loaded ahead of the one being processed
 constexpr int AGG_TILE = AGG_BLOCK * ROWS_PER_THREAD;
-constexpr int MAX_AGG_WG = 1024;
-constexpr int64_t MIN_ROWS_PER_WG = 16 * (int64_t)AGG_TILE;
+constexpr int MAX_AGG_WG = 256;
+constexpr int64_t MIN_ROWS_PER_WG = 4 * (int64_t)AGG_TILE;
 // A bin word takes at most (rows of one workgroup) units of magnitude
 // <= 2^(W-1) <= 2^39; 2^23 rows keep it below 2^62.
 constexpr int64_t MAX_ROWS_PER_WG = (int64_t)1 << 23;
-constexpr size_t LDS_BIN_BUDGET = 64 * 1024;
+constexpr size_t LDS_BIN_BUDGET = 64 * 1024 - 256;  // leaves room for static LDS
 constexpr size_t REPLICA_BUDGET = 32 * 1024;
-constexpr int MERGE_GROUPS = 64;     // groups per merge block (one per lane)
-constexpr int MERGE_WAVES = 4;
-constexpr int MERGE_PARTS = 32;      // partials reduced per level-1 block
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -65,32 +64,34 @@ __device__ __forceinline__ void vload(const T* __restrict__ p, T* out) {
 }
 
 // Loads the ROWS_PER_THREAD rows of this thread in the tile starting at
-// `base`: unit u covers rows base + (u*BLOCK + tid)*VEC + [0, VEC), so each
-// vector load instruction of a wave reads one contiguous span.  Rows at or
-// beyond `end` are flagged out of range.
+// `base`: unit u covers rows base + off[u] + [0, VEC) with off[u] =
+// (u*BLOCK + tid)*VEC, so each vector load instruction of a wave reads one
+// contiguous span (the tile base is uniform, the offsets are 32-bit).  Rows
+// at or beyond `end` are flagged out of range.
 template <class KT, class VT, int VEC, int BLOCK>
 __device__ __forceinline__ uint32_t load_tile(const KT* __restrict__ keys, const VT* __restrict__ vals,
-                                              int64_t base, int64_t end, KT* k, VT* v) {
+                                              int64_t base, int64_t end, KT* k, VT* v, const uint32_t* off) {
     constexpr int U = ROWS_PER_THREAD / VEC;
-    const int tid = threadIdx.x;
+    const KT* kb = keys + base;
+    const VT* vb = vals + base;
     uint32_t inr = 0;
     if (base + (int64_t)BLOCK * ROWS_PER_THREAD <= end) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t row = base + ((int64_t)u * BLOCK + tid) * VEC;
-            vload<KT, VEC>(keys + row, k + u * VEC);
-            vload<VT, VEC>(vals + row, v + u * VEC);
+            vload<KT, VEC>(kb + off[u], k + u * VEC);
+            vload<VT, VEC>(vb + off[u], v + u * VEC);
         }
         inr = (1u << ROWS_PER_THREAD) - 1;
     } else {
+        const uint32_t lim = (uint32_t)(end - base);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
-                const int64_t row = base + ((int64_t)u * BLOCK + tid) * VEC + e;
-                if (row < end) {
-                    k[u * VEC + e] = keys[row];
-                    v[u * VEC + e] = vals[row];
+                const uint32_t row = off[u] + e;
+                if (row < lim) {
+                    k[u * VEC + e] = kb[row];
+                    v[u * VEC + e] = vb[row];
                     inr |= 1u << (u * VEC + e);
                 } else {
                     k[u * VEC + e] = 0;
@@ -115,222 +116,509 @@ __device__ __forceinline__ void report(uint32_t* status, uint32_t err) {
 
 // ------------------------------------------------------ the hot kernel
 //
-// LDS: A[G] (top each group's bins are aligned to), P[G] (pending top,
-// raised with ds_max during a tile), bins[L][G][R] int64 (R replicas, lane
-// r uses replica lane % R to spread contention when groups are few).
+// LDS layout (G real groups plus one trash slot G that absorbs skipped
+// rows, so the deposit loop has no per-row branch):
+//   bins[G+1][R][L]  int64 level sums; lane r deposits into replica r % R
+//                    (R > 1 only when groups are few, to spread contention)
+//   TOP[G+1]         {top index, high word of the level-0 extractor}
+//   P[G+1]           pending top, raised with ds_max while a tile is read
+// A workgroup-uniform fast path applies while every group sits at the same
+// top Ju ("uni"): then no per-row LDS read of the top is needed.
+struct AggShared {
+    int newmax;     // largest top after a realignment
+    int cnt;        // groups at newmax
+    int flag[3];    // "some top was raised" per synchronisation (3 rotating slots)
+    int spills[3];  // rows deposited into the spill array, per synchronisation
+};
+
+__device__ __forceinline__ uint32_t extractor_hi_of(double*, int top) {
+    return extractor_hi((double*)0, Fmt<double>::B + top * Fmt<double>::W);
+}
+__device__ __forceinline__ uint32_t extractor_hi_of(float*, int top) {
+    return extractor_hi((float*)0, Fmt<float>::B + top * Fmt<float>::W);
+}
+
+// Units of one value given the extractor bits of its level 0 (see
+// extract_units): the extractor of level l is 2^(l*W) smaller.
+template <int L>
+__device__ __forceinline__ void extract_from_hi(double b, uint32_t h0, long long* k) {
+    double r = b;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const uint32_t mh = h0 - (uint32_t)(l * Fmt<double>::W) * (1u << 20);
+        const double M = __hiloint2double((int)mh, 0);
+        const double s = r + M;
+        if (l + 1 < L) {
+            const double t = s - M;
+            r = r - t;
+        }
+        const uint64_t sb = (uint64_t)__double_as_longlong(s);
+        k[l] = (long long)(((uint64_t)((uint32_t)(sb >> 32) - mh) << 32) | (sb & 0xffffffffull));
+    }
+}
+template <int L>
+__device__ __forceinline__ void extract_from_hi(float b, uint32_t b0, long long* k) {
+    float r = b;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const uint32_t mb = b0 - (uint32_t)(l * Fmt<float>::W) * (1u << 23);
+        const float M = __uint_as_float(mb);
+        const float s = r + M;
+        k[l] = (long long)(int32_t)(__float_as_uint(s) - mb);
+        if (l + 1 < L) {
+            const float t = s - M;
+            r = r - t;
+        }
+    }
+}
+
+// Smallest top index able to take b (jreq_of_exp) from the raw v_frexp
+// exponent f = e + 1 of a finite nonzero value, branch-free: with
+// x = f + m - W + 2 - B + W - 2 in [1, 2^11], floor(x / W) equals
+// (x * ceil(2^16 / W)) >> 16 for W = 40 and W = 18 on that whole range;
+// one 24-bit multiply-add.
+template <class AT>
+__device__ __forceinline__ int jreq_raw(int f) {
+    typedef Fmt<AT> F;
+    constexpr int mul = (65536 + F::W - 1) / F::W;
+    constexpr int add = (F::m - F::W + 2 - F::B + F::W - 2) * mul;
+    return (int)((uint32_t)__mul24(f, mul) + (uint32_t)add) >> 16;
+}
+__device__ __forceinline__ int frexp_raw(double v) { return __builtin_amdgcn_frexp_exp(v); }
+__device__ __forceinline__ int frexp_raw(float v) { return __builtin_amdgcn_frexp_expf(v); }
+
+// Per-row classification of a tile.  A row is deposited when its key is a
+// group id, its value finite, nonzero and inside the domain of AT; other
+// rows go to the trash slot G with required top 0.  `clean` stays true
+// while no row of this lane is an error (zero values are not errors).
+template <bool FULL, class KT, class VT, class AT>
+__device__ __forceinline__ void classify_rows(const KT* kc, const VT* vc, uint32_t inr, int G, int* gi, int* ji,
+                                              bool& clean) {
+#pragma unroll
+    for (int i = 0; i < ROWS_PER_THREAD; ++i) {
+        const VT v = vc[i];
+        const bool in = FULL || ((inr >> i) & 1u);
+        const bool kok = (uint64_t)(int64_t)kc[i] < (uint64_t)G;
+        const bool fin = finite_val(v);
+        const bool nz = v != (VT)0;
+        const int j = jreq_raw<AT>(frexp_raw(v));
+        const bool dom = j <= Fmt<AT>::JMAX;
+        const bool use = in && kok && fin && nz && dom;
+        clean = clean && (!in || (kok && fin && (dom || !nz)));
+        gi[i] = use ? (int)kc[i] : G;
+        ji[i] = use ? j : 0;
+    }
+}
+
+// Status bits of the error rows among this lane's rows (slow path).
+template <class KT, class VT, class AT>
+__device__ __forceinline__ uint32_t error_bits(const KT* kc, const VT* vc, uint32_t inr, int G) {
+    uint32_t e = 0;
+    for (int i = 0; i < ROWS_PER_THREAD; ++i) {
+        if (!((inr >> i) & 1u)) continue;
+        const VT v = vc[i];
+        if ((uint64_t)(int64_t)kc[i] >= (uint64_t)G) e |= ERR_KEY;
+        if (!finite_val(v))
+            e |= ERR_NONFINITE;
+        else if (v != (VT)0 && jreq_raw<AT>(frexp_raw(v)) > Fmt<AT>::JMAX)
+            e |= ERR_RANGE;
+    }
+    return e;
+}
+
+// Exact add of a unit into a spill word pair {w, H} holding H * 2^64 + w
+// (w unsigned): the atomic add returns the old w, from which the carry out
+// of this add (-1, 0 or +1) follows; it is added to H.
+__device__ __forceinline__ void spill_add(unsigned long long* w, long long k) {
+    const unsigned long long old = atomicAdd(w, (unsigned long long)k);
+    const unsigned long long nw = old + (unsigned long long)k;
+    const long long c = (k >= 0) ? (nw < old ? 1 : 0) : (nw > old ? -1 : 0);
+    if (c) atomicAdd(w + 1, (unsigned long long)c);
+}
+
+// A row whose group's bins are aligned below its required top: its units
+// are extracted at its own top jr (own-window deposit) and added into the
+// spill array at their absolute lattice indices jr - l.  Extraction at any
+// top between jr and the group's final top gives the same units at every
+// lattice index the final state keeps, so nothing has to move later.
+template <class AT, int L>
+__device__ __forceinline__ void spill_row(unsigned long long* __restrict__ spill, int g, AT v, int jr) {
+    constexpr int NJ = Fmt<AT>::JMAX + 1;
+    long long k[L];
+    extract_from_hi<L>(v, extractor_hi_of((AT*)0, jr), k);
+#pragma unroll
+    for (int l = 0; l < L; ++l) spill_add(spill + ((size_t)g * NJ + (jr - l)) * 2, k[l]);
+}
+
+constexpr int EPOCH_TILES = 16;  // tiles between synchronisations in epoch mode
+constexpr int QUIET_TILES = 1;   // quiet per-tile synchronisations before epoch mode
+
 template <class KT, class VT, class AT, int L, int VEC>
 __global__ void __launch_bounds__(AGG_BLOCK) k_agg_lds(const KT* __restrict__ keys, const VT* __restrict__ vals,
                                                        int64_t n, int G, int R, int64_t chunk,
                                                        int* __restrict__ ptop, long long* __restrict__ pK,
+                                                       unsigned long long* __restrict__ spill,
                                                        uint32_t* __restrict__ status) {
     typedef Fmt<AT> F;
+    constexpr int U = ROWS_PER_THREAD / VEC;
     extern __shared__ __align__(16) unsigned char smem[];
     long long* bins = reinterpret_cast<long long*>(smem);
-    int* A = reinterpret_cast<int*>(bins + (size_t)L * G * R);
-    int* P = A + G;
+    int2* TOP = reinterpret_cast<int2*>(bins + (size_t)(G + 1) * R * L);
+    int* P = reinterpret_cast<int*>(TOP + (G + 1));
+    __shared__ AggShared sh;
 
     const int tid = threadIdx.x;
     const int rep = (tid & 63) & (R - 1);
-    for (int i = tid; i < L * G * R; i += AGG_BLOCK) bins[i] = 0;
+    const uint32_t gstride = (uint32_t)(R * L * 8);  // bytes per group in bins
+    const uint32_t lane_off = (uint32_t)(rep * L * 8);
+    for (int i = tid; i < (G + 1) * R * L; i += AGG_BLOCK) bins[i] = 0;
+    const uint32_t h_init = extractor_hi_of((AT*)0, L - 1);
     for (int i = tid; i < G; i += AGG_BLOCK) {
-        A[i] = L - 1;
+        TOP[i] = make_int2(L - 1, (int)h_init);
         P[i] = L - 1;
     }
+    if (tid == 0) {
+        TOP[G] = make_int2(F::JMAX, (int)extractor_hi_of((AT*)0, F::JMAX));  // trash slot: never raised
+        P[G] = F::JMAX;
+        sh.newmax = L - 1;
+        sh.cnt = G;
+        for (int q = 0; q < 3; ++q) sh.flag[q] = sh.spills[q] = 0;
+    }
     __syncthreads();
+
+    // workgroup-uniform state
+    bool uni = true;   // all groups aligned to top Ju
+    int Ju = L - 1;
+    uint32_t hu = h_init;
+    int sync = 0;      // synchronisations so far (selects the flag slot)
+    int epoch_left = 0;  // tiles left in the current epoch (0: per-tile mode)
+    int quiet = 0;     // consecutive per-tile synchronisations without a raise
+
+    // Synchronisation point: all deposits before it are done.  If a top was
+    // raised since the last one, realign every group with P > TOP (its levels
+    // move down by the rise, the lowest fall off: the level shift of Alg. 1)
+    // and recompute whether all groups share one top.  Returns whether rows
+    // went to the spill array since the last synchronisation.
+    auto synchronise = [&](int& spilled) {
+        __syncthreads();
+        const int f = sh.flag[sync % 3];
+        spilled = sh.spills[sync % 3];
+        if (tid == 0) {  // slot (sync+2)%3 was read at the previous synchronisation
+            sh.flag[(sync + 2) % 3] = 0;   // and is next written after the following one
+            sh.spills[(sync + 2) % 3] = 0;
+        }
+        ++sync;
+        if (!f) return false;
+        int m = -1;
+        for (int g = tid; g < G; g += AGG_BLOCK) {
+            const int p = P[g];
+            int top = TOP[g].x;
+            if (p > top) {
+                const int d = p - top;
+                for (int r = 0; r < R; ++r) {
+                    long long* w = bins + ((size_t)g * R + r) * L;
+#pragma unroll
+                    for (int l = L - 1; l >= 0; --l) w[l] = (l - d >= 0) ? w[l - d] : 0;
+                }
+                TOP[g] = make_int2(p, (int)extractor_hi_of((AT*)0, p));
+                top = p;
+            }
+            m = max(m, top);
+        }
+        if (tid == 0) sh.cnt = 0;
+        atomicMax(&sh.newmax, m);  // newmax only grows: tops never fall
+        __syncthreads();
+        const int nm = sh.newmax;
+        int c = 0;
+        for (int g = tid; g < G; g += AGG_BLOCK) c += (TOP[g].x == nm);
+        if (c) atomicAdd(&sh.cnt, c);
+        __syncthreads();
+        uni = (sh.cnt == G);
+        Ju = nm;
+        hu = extractor_hi_of((AT*)0, Ju);
+        return true;
+    };
 
     const int64_t c0 = (int64_t)blockIdx.x * chunk;
     const int64_t c1 = (c0 + chunk < n) ? c0 + chunk : n;
     uint32_t err = 0;
 
-    KT kc[ROWS_PER_THREAD], kn[ROWS_PER_THREAD];
-    VT vc[ROWS_PER_THREAD], vn[ROWS_PER_THREAD];
-    uint32_t inr_c = 0, inr_n = 0;
-    if (c0 < c1) inr_c = load_tile<KT, VT, VEC, AGG_BLOCK>(keys, vals, c0, c1, kc, vc);
+    uint32_t off[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) off[u] = (uint32_t)((u * AGG_BLOCK + tid) * VEC);
+
+    // software pipeline: tiles base+AGG_TILE .. base+PREFETCH*AGG_TILE are in
+    // flight (in registers) while tile `base` is processed
+    KT kb[PREFETCH + 1][ROWS_PER_THREAD];
+    VT vb[PREFETCH + 1][ROWS_PER_THREAD];
+    uint32_t inr[PREFETCH + 1];
+#pragma unroll
+    for (int q = 0; q <= PREFETCH; ++q) inr[q] = 0;
+#pragma unroll
+    for (int q = 0; q < PREFETCH; ++q)
+        if (c0 + (int64_t)q * AGG_TILE < c1)
+            inr[q] = load_tile<KT, VT, VEC, AGG_BLOCK>(keys, vals, c0 + (int64_t)q * AGG_TILE, c1, kb[q], vb[q], off);
 
     for (int64_t base = c0; base < c1; base += AGG_TILE) {
-        // prefetch the next tile while this one is processed
-        const int64_t nb = base + AGG_TILE;
-        if (nb < c1) inr_n = load_tile<KT, VT, VEC, AGG_BLOCK>(keys, vals, nb, c1, kn, vn);
+        const int64_t nb = base + (int64_t)PREFETCH * AGG_TILE;
+        if (nb < c1) inr[PREFETCH] = load_tile<KT, VT, VEC, AGG_BLOCK>(keys, vals, nb, c1, kb[PREFETCH], vb[PREFETCH], off);
+        const KT* kc = kb[0];
+        const VT* vc = vb[0];
+        const uint32_t inr_c = inr[0];
 
-        int g[ROWS_PER_THREAD], a[ROWS_PER_THREAD];
-        uint32_t ok = 0, first = 0;
-        int raise = 0;
-#pragma unroll
-        for (int i = 0; i < ROWS_PER_THREAD; ++i) {
-            const bool in = (inr_c >> i) & 1u;
-            const VT v = vc[i];
-            const bool kok = (uint64_t)(int64_t)kc[i] < (uint64_t)G;
-            const bool fin = finite_val(v);
-            const int j = jreq_of_exp<AT>(exp_of(v));
-            const bool dom = j <= F::JMAX;
-            err |= (in && !kok) ? ERR_KEY : 0u;
-            err |= (in && !fin) ? ERR_NONFINITE : 0u;
-            err |= (in && fin && v != (VT)0 && !dom) ? ERR_RANGE : 0u;
-            const bool use = in && kok && fin && dom && v != (VT)0;
-            g[i] = use ? (int)kc[i] : 0;
-            a[i] = 0;
-            if (use) {
-                ok |= 1u << i;
-                a[i] = A[g[i]];
-                if (j > a[i]) {
-                    raise = 1;
-                    const int old = atomicMax(&P[g[i]], j);
-                    if (old == a[i]) first |= 1u << i;  // first raiser realigns
-                }
-            }
-        }
-        if (__syncthreads_or(raise)) {
-            // realign: move each raised group's levels down by the rise;
-            // the lowest ones fall off (the level shift of Alg. 1)
+        // classify: group (trash slot G for skipped rows) and required top
+        int gi[ROWS_PER_THREAD], ji[ROWS_PER_THREAD];
+        bool clean = true;  // no row of this lane is an error row
+        if (base + AGG_TILE <= c1)
+            classify_rows<true, KT, VT, AT>(kc, vc, inr_c, G, gi, ji, clean);
+        else
+            classify_rows<false, KT, VT, AT>(kc, vc, inr_c, G, gi, ji, clean);
+        if (!clean) err |= error_bits<KT, VT, AT>(kc, vc, base + AGG_TILE <= c1 ? 0xffu : inr_c, G);
+
+        // tops of the rows' groups
+        int ai[ROWS_PER_THREAD];
+        uint32_t hi_[ROWS_PER_THREAD];
+        if (uni) {
 #pragma unroll
             for (int i = 0; i < ROWS_PER_THREAD; ++i) {
-                if ((first >> i) & 1u) {
-                    const int gg = g[i];
-                    const int d = P[gg] - A[gg];
-                    for (int r = 0; r < R; ++r) {
+                ai[i] = Ju;
+                hi_[i] = hu;
+            }
+        } else {
 #pragma unroll
-                        for (int l = L - 1; l >= 0; --l) {
-                            const long long x = (l - d >= 0) ? bins[((size_t)(l - d) * G + gg) * R + r] : 0;
-                            bins[((size_t)l * G + gg) * R + r] = x;
-                        }
-                    }
-                    A[gg] = P[gg];
+            for (int i = 0; i < ROWS_PER_THREAD; ++i) {
+                const int2 tp = TOP[gi[i]];
+                ai[i] = tp.x;
+                hi_[i] = (uint32_t)tp.y;
+            }
+        }
+        bool raise = false;
+#pragma unroll
+        for (int i = 0; i < ROWS_PER_THREAD; ++i) raise = raise || (ji[i] > ai[i]);
+        if (epoch_left == 0) {
+            // per-tile mode: raise the tops, synchronise, then deposit
+            if (raise) {
+                sh.flag[sync % 3] = 1;
+#pragma unroll
+                for (int i = 0; i < ROWS_PER_THREAD; ++i)
+                    if (ji[i] > ai[i]) atomicMax(&P[gi[i]], ji[i]);
+            }
+            int sp;
+            const bool moved = synchronise(sp);
+            quiet = moved ? 0 : quiet + 1;
+            if (quiet >= QUIET_TILES) epoch_left = EPOCH_TILES;
+            if (moved) {
+                if (uni) {
+#pragma unroll
+                    for (int i = 0; i < ROWS_PER_THREAD; ++i) hi_[i] = hu;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < ROWS_PER_THREAD; ++i) hi_[i] = (uint32_t)TOP[gi[i]].y;
                 }
             }
-            __syncthreads();
+        } else if (raise) {
+            // epoch mode: rows above their group's top go to the spill array
+            int ns = 0;
 #pragma unroll
-            for (int i = 0; i < ROWS_PER_THREAD; ++i)
-                if ((ok >> i) & 1u) a[i] = A[g[i]];
-        }
-#pragma unroll
-        for (int i = 0; i < ROWS_PER_THREAD; ++i) {
-            if ((ok >> i) & 1u) {
-                long long k[L];
-                extract_units<L>((AT)vc[i], a[i], k);
-#pragma unroll
-                for (int l = 0; l < L; ++l)
-                    atomicAdd(reinterpret_cast<unsigned long long*>(&bins[((size_t)l * G + g[i]) * R + rep]),
-                              (unsigned long long)k[l]);
+            for (int i = 0; i < ROWS_PER_THREAD; ++i) {
+                if (ji[i] > ai[i]) {
+                    atomicMax(&P[gi[i]], ji[i]);
+                    spill_row<AT, L>(spill, gi[i], (AT)vc[i], ji[i]);
+                    gi[i] = G;  // nothing more for the bins
+                    ++ns;
+                }
             }
+            sh.flag[sync % 3] = 1;
+            atomicAdd(&sh.spills[sync % 3], ns);
         }
+        // extract and deposit (skipped rows go to the trash slot)
 #pragma unroll
         for (int i = 0; i < ROWS_PER_THREAD; ++i) {
-            kc[i] = kn[i];
-            vc[i] = vn[i];
+            long long k[L];
+            extract_from_hi<L>((AT)vc[i], hi_[i], k);
+            unsigned long long* w =
+                reinterpret_cast<unsigned long long*>(smem + __umul24((uint32_t)gi[i], gstride) + lane_off);
+#pragma unroll
+            for (int l = 0; l < L; ++l) atomicAdd(w + l, (unsigned long long)k[l]);
         }
-        inr_c = inr_n;
+        if (epoch_left > 0 && --epoch_left == 0) {
+            int sp;
+            synchronise(sp);
+            // many spills: the tops are still moving, go back to per-tile mode
+            epoch_left = (sp > AGG_TILE / 16) ? 0 : EPOCH_TILES;
+            quiet = 0;
+        }
+#pragma unroll
+        for (int q = 0; q < PREFETCH; ++q) {
+#pragma unroll
+            for (int i = 0; i < ROWS_PER_THREAD; ++i) {
+                kb[q][i] = kb[q + 1][i];
+                vb[q][i] = vb[q + 1][i];
+            }
+            inr[q] = inr[q + 1];
+        }
     }
-    __syncthreads();
-    for (int gg = tid; gg < G; gg += AGG_BLOCK) {
-        ptop[(size_t)blockIdx.x * G + gg] = A[gg];
+    // final synchronisation: tops include every spilled row, bins aligned
+    int sp;
+    synchronise(sp);
+    for (int g = tid; g < G; g += AGG_BLOCK) {
+        ptop[(size_t)blockIdx.x * G + g] = TOP[g].x;
 #pragma unroll
         for (int l = 0; l < L; ++l) {
             long long s = 0;
-            for (int r = 0; r < R; ++r) s += bins[((size_t)l * G + gg) * R + r];
-            pK[((size_t)blockIdx.x * L + l) * G + gg] = s;
+            for (int r = 0; r < R; ++r) s += bins[((size_t)g * R + r) * L + l];
+            pK[((size_t)blockIdx.x * L + l) * G + g] = s;
         }
     }
     report(status, err);
 }
 
+// Zeroes the spill array before an aggregation pass.
+__global__ void __launch_bounds__(256) k_zero(unsigned long long* __restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = 0;
+}
+
 // ------------------------------------------------------------- merging
 //
-// Level 1: block (bx, by) reduces partials [by*MERGE_PARTS, ...) for groups
-// bx*64 + lane.  Output per (by, g): common top and, per level, the exact
-// sum split as hi = sum(K >> CARRY), lo = sum(K & mask) (no overflow for up
-// to 2^13 partials).
+// The workgroup partials (top, K[L]) of every group are folded into the
+// caller's canonical state in two launches (operator+=(repro) over all
+// partials).  Every step is exact integer arithmetic, so the split into
+// blocks does not change any bit.
+//
+// Level 1 (k_merge_l1): block (x, y) takes groups x*64 .. x*64+63 (one per
+// lane) and partials y*PB .. y*PB+PB-1 (spread over the 4 waves).  It forms
+// their common top J (the largest), moves each partial's levels down by its
+// distance to J and adds the level sums split as hi = sum(K >> CARRY),
+// lo = sum(K & (2^CARRY - 1)) (no int64 overflow: |K| < 2^62 per partial).
+// Level 2 (k_merge_l2): one lane per group adds the level-1 results and the
+// caller's state the same way and writes the canonical (S, C).
+constexpr int M1_GROUPS = 64, M1_WAVES = 4;
+constexpr int M2_GROUPS = 16, M2_SLICES = 16;
+
 template <class AT, int L>
-__global__ void __launch_bounds__(MERGE_GROUPS* MERGE_WAVES)
-    k_merge_l1(const int* __restrict__ ptop, const long long* __restrict__ pK, int nparts, int G,
+__global__ void __launch_bounds__(M1_GROUPS* M1_WAVES)
+    k_merge_l1(const int* __restrict__ ptop, const long long* __restrict__ pK, int nparts, int PB, int G,
                int* __restrict__ qtop, long long* __restrict__ qhi, long long* __restrict__ qlo) {
     constexpr int c = Fmt<AT>::CARRY;
-    __shared__ int sJ[MERGE_WAVES][MERGE_GROUPS];
-    __shared__ long long sH[MERGE_WAVES][L][MERGE_GROUPS], sL[MERGE_WAVES][L][MERGE_GROUPS];
+    __shared__ int sJ[M1_WAVES][M1_GROUPS];
+    __shared__ long long sH[M1_WAVES][L][M1_GROUPS], sLo[M1_WAVES][L][M1_GROUPS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = blockIdx.x * MERGE_GROUPS + lane;
+    const int g = blockIdx.x * M1_GROUPS + lane;
     const bool gv = g < G;
-    const int p0 = blockIdx.y * MERGE_PARTS;
-    const int p1 = min(nparts, p0 + MERGE_PARTS);
+    const int gg = gv ? g : 0;  // clamped: loads stay in bounds, results unused
+    const int p0 = blockIdx.y * PB;
+    const int p1 = min(nparts, p0 + PB);
     int J = L - 1;
-    if (gv)
-        for (int p = p0 + wave; p < p1; p += MERGE_WAVES) J = max(J, ptop[(size_t)p * G + g]);
+    for (int p = p0 + wave; p < p1; p += M1_WAVES) J = max(J, ptop[(size_t)p * G + gg]);
     sJ[wave][lane] = J;
     __syncthreads();
 #pragma unroll
-    for (int w = 0; w < MERGE_WAVES; ++w) J = max(J, sJ[w][lane]);
+    for (int w = 0; w < M1_WAVES; ++w) J = max(J, sJ[w][lane]);
     long long hi[L], lo[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) hi[l] = lo[l] = 0;
-    if (gv) {
-        for (int p = p0 + wave; p < p1; p += MERGE_WAVES) {
-            const int d = J - ptop[(size_t)p * G + g];
+    for (int p = p0 + wave; p < p1; p += M1_WAVES) {
+        const int d = J - ptop[(size_t)p * G + gg];
+        long long x[L];
 #pragma unroll
-            for (int l = 0; l < L; ++l) {
-                if (l - d >= 0) {
-                    const long long x = pK[((size_t)p * L + (l - d)) * G + g];
-                    hi[l] += x >> c;
-                    lo[l] += x & ((1ll << c) - 1);
-                }
-            }
+        for (int l = 0; l < L; ++l) x[l] = pK[((size_t)p * L + l) * G + gg];
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            // level l of the result is level l - d of this partial
+            long long v = 0;
+#pragma unroll
+            for (int q = 0; q < L; ++q) v = (q == l - d) ? x[q] : v;
+            hi[l] += v >> c;
+            lo[l] += v & ((1ll << c) - 1);
         }
     }
 #pragma unroll
     for (int l = 0; l < L; ++l) {
         sH[wave][l][lane] = hi[l];
-        sL[wave][l][lane] = lo[l];
+        sLo[wave][l][lane] = lo[l];
     }
     __syncthreads();
-    if (wave == 0 && gv) {
-#pragma unroll
-        for (int l = 0; l < L; ++l) {
-            long long h = 0, o = 0;
-#pragma unroll
-            for (int w = 0; w < MERGE_WAVES; ++w) {
-                h += sH[w][l][lane];
-                o += sL[w][l][lane];
-            }
-            qhi[((size_t)blockIdx.y * L + l) * G + g] = h;
-            qlo[((size_t)blockIdx.y * L + l) * G + g] = o;
-        }
-        qtop[(size_t)blockIdx.y * G + g] = J;
-    }
-}
-
-// Level 2: one thread per group folds the reduced partials (hi, lo form, or
-// raw K when RAW) into the caller's canonical state and renormalises.
-template <class AT, int L, bool RAW>
-__global__ void __launch_bounds__(256)
-    k_merge_l2(const int* __restrict__ qtop, const long long* __restrict__ qhi, const long long* __restrict__ qlo,
-               int nparts, int G, AT* __restrict__ S, long long* __restrict__ C) {
-    typedef Fmt<AT> F;
-    constexpr int c = F::CARRY;
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= G) return;
-    const int ts = state_top(S[g]);
-    int J = ts;
-    for (int p = 0; p < nparts; ++p) J = max(J, qtop[(size_t)p * G + g]);
-    long long hi[L], lo[L];
-    const int ds = J - ts;
+    if (wave != 0 || !gv) return;
 #pragma unroll
     for (int l = 0; l < L; ++l) {
-        hi[l] = (l - ds >= 0) ? C[(size_t)(l - ds) * G + g] : 0;
-        lo[l] = (l - ds >= 0) ? state_lo(S[(size_t)(l - ds) * G + g]) : 0;
+        long long h = 0, o = 0;
+#pragma unroll
+        for (int w = 0; w < M1_WAVES; ++w) {
+            h += sH[w][l][lane];
+            o += sLo[w][l][lane];
+        }
+        qhi[((size_t)blockIdx.y * L + l) * G + g] = h;
+        qlo[((size_t)blockIdx.y * L + l) * G + g] = o;
     }
-    for (int p = 0; p < nparts; ++p) {
-        const int d = J - qtop[(size_t)p * G + g];
+    qtop[(size_t)blockIdx.y * G + g] = J;
+}
+
+template <class AT, int L>
+__global__ void __launch_bounds__(M2_GROUPS* M2_SLICES)
+    k_merge_l2(const int* __restrict__ qtop, const long long* __restrict__ qhi, const long long* __restrict__ qlo,
+               int nq, int G, const unsigned long long* __restrict__ spill, AT* __restrict__ S,
+               long long* __restrict__ C) {
+    constexpr int NJ = Fmt<AT>::JMAX + 1;
+    typedef Fmt<AT> F;
+    __shared__ int sJ[M2_SLICES][M2_GROUPS];
+    __shared__ long long sH[M2_SLICES][L][M2_GROUPS], sLo[M2_SLICES][L][M2_GROUPS];
+    const int lane = threadIdx.x % M2_GROUPS, sl = threadIdx.x / M2_GROUPS;
+    const int g = blockIdx.x * M2_GROUPS + lane;
+    const bool gv = g < G;
+    const int gg = gv ? g : 0;
+    const int ts = state_top(S[gg]);
+    int J = ts;
+    for (int q = sl; q < nq; q += M2_SLICES) J = max(J, qtop[(size_t)q * G + gg]);
+    sJ[sl][lane] = J;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < M2_SLICES; ++w) J = max(J, sJ[w][lane]);
+    long long hi[L], lo[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) hi[l] = lo[l] = 0;
+    for (int q = sl; q < nq; q += M2_SLICES) {
+        const int d = J - qtop[(size_t)q * G + gg];
+        long long xh[L], xl[L];
 #pragma unroll
         for (int l = 0; l < L; ++l) {
-            if (l - d >= 0) {
-                if (RAW) {
-                    const long long x = qhi[((size_t)p * L + (l - d)) * G + g];
-                    hi[l] += x >> c;
-                    lo[l] += x & ((1ll << c) - 1);
-                } else {
-                    hi[l] += qhi[((size_t)p * L + (l - d)) * G + g];
-                    lo[l] += qlo[((size_t)p * L + (l - d)) * G + g];
+            xh[l] = qhi[((size_t)q * L + l) * G + gg];
+            xl[l] = qlo[((size_t)q * L + l) * G + gg];
+        }
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+#pragma unroll
+            for (int r = 0; r < L; ++r) {
+                if (r == l - d) {
+                    hi[l] += xh[r];
+                    lo[l] += xl[r];
                 }
             }
         }
+    }
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        sH[sl][l][lane] = hi[l];
+        sLo[sl][l][lane] = lo[l];
+    }
+    __syncthreads();
+    if (sl != 0 || !gv) return;
+    const int ds = J - ts;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        long long h = (l - ds >= 0) ? C[(size_t)(l - ds) * G + g] : 0;
+        long long o = (l - ds >= 0) ? state_lo(S[(size_t)(l - ds) * G + g]) : 0;
+#pragma unroll
+        for (int w = 0; w < M2_SLICES; ++w) {
+            h += sH[w][l][lane];
+            o += sLo[w][l][lane];
+        }
+        // spilled units at lattice index J - l: H * 2^64 + w
+        const unsigned long long* sw = spill + ((size_t)g * NJ + (J - l)) * 2;
+        const i128 T = (i128)(long long)sw[1] * ((i128)1 << 64) + (i128)sw[0];
+        h += (long long)(T >> Fmt<AT>::CARRY);
+        o += (long long)(T & ((1ll << Fmt<AT>::CARRY) - 1));
+        hi[l] = h;
+        lo[l] = o;
     }
 #pragma unroll
     for (int l = 0; l < L; ++l) {
@@ -405,23 +693,30 @@ __global__ void __launch_bounds__(256) k_finalize(const AT* __restrict__ S, cons
 
 // --------------------------------------------------- plain FP64 baseline
 // Non-reproducible reference point: LDS-privatised double atomics, then
-// one global double atomic per group and workgroup.
+// one global double atomic per group and workgroup.  Its own launch shape
+// (4 workgroups of 256 threads per CU) streams at the full read bandwidth.
+constexpr int PLAIN_BLOCK = 256;
+constexpr int PLAIN_TILE = PLAIN_BLOCK * ROWS_PER_THREAD;
+constexpr int PLAIN_MAX_WG = 1024;
 template <class KT, class VT, int VEC>
-__global__ void __launch_bounds__(AGG_BLOCK) k_plain_lds(const KT* __restrict__ keys, const VT* __restrict__ vals,
+__global__ void __launch_bounds__(PLAIN_BLOCK) k_plain_lds(const KT* __restrict__ keys, const VT* __restrict__ vals,
                                                          int64_t n, int G, int64_t chunk, double* __restrict__ out,
                                                          uint32_t* __restrict__ status) {
     extern __shared__ __align__(16) unsigned char smem[];
     double* bins = reinterpret_cast<double*>(smem);
     const int tid = threadIdx.x;
-    for (int i = tid; i < G; i += AGG_BLOCK) bins[i] = 0.0;
+    for (int i = tid; i < G; i += PLAIN_BLOCK) bins[i] = 0.0;
     __syncthreads();
     const int64_t c0 = (int64_t)blockIdx.x * chunk;
     const int64_t c1 = (c0 + chunk < n) ? c0 + chunk : n;
     uint32_t err = 0;
     KT kc[ROWS_PER_THREAD];
     VT vc[ROWS_PER_THREAD];
-    for (int64_t base = c0; base < c1; base += AGG_TILE) {
-        const uint32_t inr = load_tile<KT, VT, VEC, AGG_BLOCK>(keys, vals, base, c1, kc, vc);
+    uint32_t off[ROWS_PER_THREAD / VEC];
+#pragma unroll
+    for (int u = 0; u < ROWS_PER_THREAD / VEC; ++u) off[u] = (uint32_t)((u * PLAIN_BLOCK + threadIdx.x) * VEC);
+    for (int64_t base = c0; base < c1; base += PLAIN_TILE) {
+        const uint32_t inr = load_tile<KT, VT, VEC, PLAIN_BLOCK>(keys, vals, base, c1, kc, vc, off);
 #pragma unroll
         for (int i = 0; i < ROWS_PER_THREAD; ++i) {
             const bool in = (inr >> i) & 1u;
@@ -433,13 +728,13 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_plain_lds(const KT* __restrict__ 
         }
     }
     __syncthreads();
-    for (int gg = tid; gg < G; gg += AGG_BLOCK)
+    for (int gg = tid; gg < G; gg += PLAIN_BLOCK)
         if (bins[gg] != 0.0) atomicAdd(&out[gg], bins[gg]);
     report(status, err);
 }
 
 template <class KT, class VT, int VEC>
-__global__ void __launch_bounds__(AGG_BLOCK) k_plain_global(const KT* __restrict__ keys, const VT* __restrict__ vals,
+__global__ void __launch_bounds__(PLAIN_BLOCK) k_plain_global(const KT* __restrict__ keys, const VT* __restrict__ vals,
                                                             int64_t n, int G, int64_t chunk, double* __restrict__ out,
                                                             uint32_t* __restrict__ status) {
     const int64_t c0 = (int64_t)blockIdx.x * chunk;
@@ -447,8 +742,11 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_plain_global(const KT* __restrict
     uint32_t err = 0;
     KT kc[ROWS_PER_THREAD];
     VT vc[ROWS_PER_THREAD];
-    for (int64_t base = c0; base < c1; base += AGG_TILE) {
-        const uint32_t inr = load_tile<KT, VT, VEC, AGG_BLOCK>(keys, vals, base, c1, kc, vc);
+    uint32_t off[ROWS_PER_THREAD / VEC];
+#pragma unroll
+    for (int u = 0; u < ROWS_PER_THREAD / VEC; ++u) off[u] = (uint32_t)((u * PLAIN_BLOCK + threadIdx.x) * VEC);
+    for (int64_t base = c0; base < c1; base += PLAIN_TILE) {
+        const uint32_t inr = load_tile<KT, VT, VEC, PLAIN_BLOCK>(keys, vals, base, c1, kc, vc, off);
 #pragma unroll
         for (int i = 0; i < ROWS_PER_THREAD; ++i) {
             const bool in = (inr >> i) & 1u;
@@ -479,13 +777,22 @@ inline void prof_after(hipStream_t st) {
     if (g_prof && g_prof->used < g_prof->armed) (void)hipEventRecord(g_prof->ev[2 * g_prof->used++ + 1], st);
 }
 
+// partials per level-1 block: enough blocks to fill the chip, at most 64
+inline int merge_pb(int nwg, int G) {
+    const int gx = (G + M1_GROUPS - 1) / M1_GROUPS;
+    int pb = 4;
+    while (pb < 64 && (int64_t)gx * ((nwg + pb - 1) / pb) > 1024) pb *= 2;
+    return pb;
+}
+
 struct Plan {
     int path;       // 1: LDS bins
     int nwg;        // aggregate workgroups
     int64_t chunk;  // rows per workgroup (multiple of the tile)
     int R;          // LDS bin replicas
+    int pb, nq;     // partials per level-1 merge block, level-1 results
+    size_t spill_off, spill_words;  // spill array: G x (JMAX+1) x {w, H}
     size_t lds;     // dynamic LDS bytes
-    int n_l1;       // level-1 merge blocks along the partial axis (0: skip)
     size_t ws;      // workspace bytes
 };
 
@@ -501,13 +808,13 @@ int replicas_for(int64_t G, int L) {
     return R;
 }
 
-bool make_plan(int64_t n, int64_t G, int L, Plan* p) {
+bool make_plan(int64_t n, int64_t G, int L, int jmax, Plan* p) {
     memset(p, 0, sizeof(*p));
-    const size_t lds1 = (size_t)G * L * 8 + (size_t)G * 8;
+    const size_t lds1 = (size_t)(G + 1) * L * 8 + (size_t)(G + 1) * 12;
     if (lds1 > LDS_BIN_BUDGET) return false;  // high cardinality: not on this path
     p->path = 1;
     p->R = replicas_for(G, L);
-    p->lds = (size_t)G * L * 8 * p->R + (size_t)G * 8;
+    p->lds = (size_t)(G + 1) * L * 8 * p->R + (size_t)(G + 1) * 12;
     int64_t nwg = (n + MIN_ROWS_PER_WG - 1) / MIN_ROWS_PER_WG;
     if (nwg > MAX_AGG_WG) nwg = MAX_AGG_WG;
     if (nwg < (n + MAX_ROWS_PER_WG - 1) / MAX_ROWS_PER_WG) nwg = (n + MAX_ROWS_PER_WG - 1) / MAX_ROWS_PER_WG;
@@ -517,17 +824,19 @@ bool make_plan(int64_t n, int64_t G, int L, Plan* p) {
     if (chunk < AGG_TILE) chunk = AGG_TILE;
     nwg = (n + chunk - 1) / chunk;
     if (nwg < 1) nwg = 1;
-    if (nwg > INT32_MAX / 2) return false;
+    if (nwg > 4096) return false;  // keeps the merge's int64 carry sums exact
     p->nwg = (int)nwg;
     p->chunk = chunk;
-    p->n_l1 = nwg > MERGE_PARTS ? (int)((nwg + MERGE_PARTS - 1) / MERGE_PARTS) : 0;
+    p->pb = merge_pb(p->nwg, (int)G);
+    p->nq = (p->nwg + p->pb - 1) / p->pb;
     size_t ws = 0;
     ws += align_up((size_t)nwg * G * 4, 256);          // partial tops
     ws += align_up((size_t)nwg * G * L * 8, 256);      // partial K
-    if (p->n_l1) {
-        ws += align_up((size_t)p->n_l1 * G * 4, 256);      // reduced tops
-        ws += 2 * align_up((size_t)p->n_l1 * G * L * 8, 256);  // reduced hi, lo
-    }
+    ws += align_up((size_t)p->nq * G * 4, 256);        // level-1 tops
+    ws += 2 * align_up((size_t)p->nq * G * L * 8, 256);  // level-1 hi, lo
+    p->spill_off = ws;
+    p->spill_words = (size_t)G * (jmax + 1) * 2;
+    ws += align_up(p->spill_words * 8, 256);
     p->ws = ws;
     return true;
 }
@@ -541,22 +850,17 @@ template <class AT, int L>
 int run_merge(const Plan& p, int G, unsigned char* ws, AT* S, long long* C, hipStream_t st) {
     int* ptop = reinterpret_cast<int*>(ws);
     long long* pK = reinterpret_cast<long long*>(ws + align_up((size_t)p.nwg * G * 4, 256));
-    const dim3 b2(256), g2((G + 255) / 256);
-    if (p.n_l1 == 0) {
-        hipLaunchKernelGGL((k_merge_l2<AT, L, true>), g2, b2, 0, st, ptop, pK, (const long long*)nullptr, p.nwg, G, S,
-                           C);
-        LAUNCH_CHECK();
-        return REPRO_OK;
-    }
-    unsigned char* q = ws + align_up((size_t)p.nwg * G * 4, 256) + align_up((size_t)p.nwg * G * L * 8, 256);
+    unsigned char* q = reinterpret_cast<unsigned char*>(pK) + align_up((size_t)p.nwg * G * L * 8, 256);
     int* qtop = reinterpret_cast<int*>(q);
-    long long* qhi = reinterpret_cast<long long*>(q + align_up((size_t)p.n_l1 * G * 4, 256));
+    long long* qhi = reinterpret_cast<long long*>(q + align_up((size_t)p.nq * G * 4, 256));
     long long* qlo = reinterpret_cast<long long*>(reinterpret_cast<unsigned char*>(qhi) +
-                                                  align_up((size_t)p.n_l1 * G * L * 8, 256));
-    const dim3 b1(MERGE_GROUPS * MERGE_WAVES), g1((G + MERGE_GROUPS - 1) / MERGE_GROUPS, p.n_l1);
-    hipLaunchKernelGGL((k_merge_l1<AT, L>), g1, b1, 0, st, ptop, pK, p.nwg, G, qtop, qhi, qlo);
+                                                  align_up((size_t)p.nq * G * L * 8, 256));
+    hipLaunchKernelGGL((k_merge_l1<AT, L>), dim3((G + M1_GROUPS - 1) / M1_GROUPS, p.nq), dim3(M1_GROUPS * M1_WAVES),
+                       0, st, ptop, pK, p.nwg, p.pb, G, qtop, qhi, qlo);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_merge_l2<AT, L, false>), g2, b2, 0, st, qtop, qhi, qlo, p.n_l1, G, S, C);
+    const unsigned long long* spill = reinterpret_cast<const unsigned long long*>(ws + p.spill_off);
+    hipLaunchKernelGGL((k_merge_l2<AT, L>), dim3((G + M2_GROUPS - 1) / M2_GROUPS), dim3(M2_GROUPS * M2_SLICES), 0,
+                       st, qtop, qhi, qlo, p.nq, G, spill, S, C);
     LAUNCH_CHECK();
     return REPRO_OK;
 }
@@ -571,13 +875,17 @@ int run_groupby(const void* keys, const void* values, int64_t n, int G, void* st
     const VT* v = static_cast<const VT*>(values);
     constexpr int VEC = 16 / sizeof(VT);
     const bool aligned = ((uintptr_t)k % (VEC * sizeof(KT)) == 0) && ((uintptr_t)v % 16 == 0);
+    unsigned long long* spill = reinterpret_cast<unsigned long long*>(ws + p.spill_off);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(1024, (p.spill_words + 255) / 256)), dim3(256), 0, st,
+                       spill, p.spill_words);
+    LAUNCH_CHECK();
     prof_before(st);
     if (aligned)
         hipLaunchKernelGGL((k_agg_lds<KT, VT, AT, L, VEC>), dim3(p.nwg), dim3(AGG_BLOCK), p.lds, st, k, v, n, G, p.R,
-                           p.chunk, ptop, pK, status);
+                           p.chunk, ptop, pK, spill, status);
     else
         hipLaunchKernelGGL((k_agg_lds<KT, VT, AT, L, 1>), dim3(p.nwg), dim3(AGG_BLOCK), p.lds, st, k, v, n, G, p.R,
-                           p.chunk, ptop, pK, status);
+                           p.chunk, ptop, pK, spill, status);
     LAUNCH_CHECK();
     prof_after(st);
     AT* S = static_cast<AT*>(states);
@@ -656,28 +964,28 @@ template <class KT, class VT>
 int run_plain(const void* keys, const void* values, int64_t n, int G, double* out, uint32_t* status, hipStream_t st) {
     const KT* k = static_cast<const KT*>(keys);
     const VT* v = static_cast<const VT*>(values);
-    int64_t nwg = (n + MIN_ROWS_PER_WG - 1) / MIN_ROWS_PER_WG;
-    if (nwg > MAX_AGG_WG) nwg = MAX_AGG_WG;
+    int64_t nwg = (n + 16 * PLAIN_TILE - 1) / (16 * PLAIN_TILE);
+    if (nwg > PLAIN_MAX_WG) nwg = PLAIN_MAX_WG;
     if (nwg < 1) nwg = 1;
     int64_t chunk = (n + nwg - 1) / nwg;
-    chunk = (chunk + AGG_TILE - 1) / AGG_TILE * AGG_TILE;
+    chunk = (chunk + PLAIN_TILE - 1) / PLAIN_TILE * PLAIN_TILE;
     nwg = (n + chunk - 1) / chunk;
     constexpr int VEC = 16 / sizeof(VT);
     const bool aligned = ((uintptr_t)k % (VEC * sizeof(KT)) == 0) && ((uintptr_t)v % 16 == 0);
     if ((size_t)G * 8 <= LDS_BIN_BUDGET) {
         const size_t lds = (size_t)G * 8;
         if (aligned)
-            hipLaunchKernelGGL((k_plain_lds<KT, VT, VEC>), dim3(nwg), dim3(AGG_BLOCK), lds, st, k, v, n, G, chunk, out,
+            hipLaunchKernelGGL((k_plain_lds<KT, VT, VEC>), dim3(nwg), dim3(PLAIN_BLOCK), lds, st, k, v, n, G, chunk, out,
                                status);
         else
-            hipLaunchKernelGGL((k_plain_lds<KT, VT, 1>), dim3(nwg), dim3(AGG_BLOCK), lds, st, k, v, n, G, chunk, out,
+            hipLaunchKernelGGL((k_plain_lds<KT, VT, 1>), dim3(nwg), dim3(PLAIN_BLOCK), lds, st, k, v, n, G, chunk, out,
                                status);
     } else {
         if (aligned)
-            hipLaunchKernelGGL((k_plain_global<KT, VT, VEC>), dim3(nwg), dim3(AGG_BLOCK), 0, st, k, v, n, G, chunk,
+            hipLaunchKernelGGL((k_plain_global<KT, VT, VEC>), dim3(nwg), dim3(PLAIN_BLOCK), 0, st, k, v, n, G, chunk,
                                out, status);
         else
-            hipLaunchKernelGGL((k_plain_global<KT, VT, 1>), dim3(nwg), dim3(AGG_BLOCK), 0, st, k, v, n, G, chunk, out,
+            hipLaunchKernelGGL((k_plain_global<KT, VT, 1>), dim3(nwg), dim3(PLAIN_BLOCK), 0, st, k, v, n, G, chunk, out,
                                status);
     }
     LAUNCH_CHECK();
@@ -701,7 +1009,7 @@ size_t repro_workspace_bytes(int64_t n, int64_t num_groups, repro_key_t kt, repr
     (void)vt;
     Plan p;
     if (!valid_common(num_groups, T, L) || n < 0) return 0;
-    if (!make_plan(n, num_groups, L, &p)) return 0;
+    if (!make_plan(n, num_groups, L, T == REPRO_F64 ? Fmt<double>::JMAX : Fmt<float>::JMAX, &p)) return 0;
     return p.ws;
 }
 
@@ -719,7 +1027,7 @@ int repro_groupby_sum(const void* keys, repro_key_t kt, const void* values, repr
     if (n == 0) return REPRO_OK;
     if (!keys || !values) return REPRO_EINVAL;
     Plan p;
-    if (!make_plan(n, num_groups, L, &p)) return REPRO_EINVAL;
+    if (!make_plan(n, num_groups, L, T == REPRO_F64 ? Fmt<double>::JMAX : Fmt<float>::JMAX, &p)) return REPRO_EINVAL;
     if (p.ws > 0 && (!workspace || workspace_bytes < p.ws || (uintptr_t)workspace % 256 != 0)) return REPRO_EINVAL;
     const int G = (int)num_groups;
     if (kt == REPRO_I32)
