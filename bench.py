@@ -26,6 +26,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_agg_lds_lowcard_200M_g1024_L3_pmc.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the aggregation kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel sources
+    changed since those counters were taken."""
+    import hashlib
+
+    try:
+        text = open(PMC_SUMMARY).read()
+    except OSError:
+        return None
+    vals = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("kernel_source_sha256", "traffic_")))
+    csrc = os.path.join(ROOT, "paper_1802_09883_amd", "csrc")
+    h = hashlib.sha256(open(os.path.join(csrc, "repro.hip"), "rb").read() +
+                       open(os.path.join(csrc, "repro_device.hpp"), "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256") != h or "traffic_bytes_per_launch" not in vals:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
 
 
 def log(msg):
@@ -130,7 +150,7 @@ def main():
     alg_k64 = n * (4 + 8)
     ach_gbs = alg_k64 / (np.mean(k64) * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(ach_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(ach_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                 "kernel": "k_agg_lds<int32,f64,f64,L=3> (f64 column)",
                 "kernel_ms": round(float(np.mean(k64)), 4),
                 "alg_bytes_per_launch": alg_k64}
