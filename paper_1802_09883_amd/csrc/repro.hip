@@ -39,7 +39,7 @@ constexpr int64_t MIN_ROWS_PER_WG = 4 * (int64_t)AGG_TILE;
 // A bin word takes at most (rows of one workgroup) units of magnitude
 // <= 2^(W-1) <= 2^39; 2^23 rows keep it below 2^62.
 constexpr int64_t MAX_ROWS_PER_WG = (int64_t)1 << 23;
-constexpr size_t LDS_BIN_BUDGET = 64 * 1024 - 256;  // leaves room for static LDS
+constexpr size_t LDS_BIN_BUDGET = 150 * 1024;  // of gfx950's 160 KiB per workgroup
 constexpr size_t REPLICA_BUDGET = 32 * 1024;
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -253,19 +253,19 @@ __device__ __forceinline__ void spill_row(unsigned long long* __restrict__ spill
 constexpr int EPOCH_TILES = 16;  // tiles between synchronisations in epoch mode
 constexpr int QUIET_TILES = 1;   // quiet per-tile synchronisations before epoch mode
 
-template <class KT, class VT, class AT, int L, int VEC>
-__global__ void __launch_bounds__(AGG_BLOCK) k_agg_lds(const KT* __restrict__ keys, const VT* __restrict__ vals,
-                                                       int64_t n, int G, int R, int64_t chunk,
-                                                       int* __restrict__ ptop, long long* __restrict__ pK,
-                                                       unsigned long long* __restrict__ spill,
-                                                       uint32_t* __restrict__ status) {
+// The aggregation of rows [c0, c1) into LDS by one workgroup (the hot loop
+// of both aggregation kernels).  On return the bins are aligned to every
+// group's top (TOP), and the lane's status bits are returned.  EPOCH
+// enables epoch mode, which needs the spill array.
+template <class KT, class VT, class AT, int L, int VEC, bool EPOCH>
+__device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys, const VT* __restrict__ vals,
+                                                    int64_t c0, int64_t c1, int G, int R, unsigned char* smem,
+                                                    AggShared& sh, unsigned long long* __restrict__ spill) {
     typedef Fmt<AT> F;
     constexpr int U = ROWS_PER_THREAD / VEC;
-    extern __shared__ __align__(16) unsigned char smem[];
     long long* bins = reinterpret_cast<long long*>(smem);
     int2* TOP = reinterpret_cast<int2*>(bins + (size_t)(G + 1) * R * L);
     int* P = reinterpret_cast<int*>(TOP + (G + 1));
-    __shared__ AggShared sh;
 
     const int tid = threadIdx.x;
     const int rep = (tid & 63) & (R - 1);
@@ -339,8 +339,6 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_lds(const KT* __restrict__ ke
         return true;
     };
 
-    const int64_t c0 = (int64_t)blockIdx.x * chunk;
-    const int64_t c1 = (c0 + chunk < n) ? c0 + chunk : n;
     uint32_t err = 0;
 
     uint32_t off[U];
@@ -406,7 +404,7 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_lds(const KT* __restrict__ ke
             int sp;
             const bool moved = synchronise(sp);
             quiet = moved ? 0 : quiet + 1;
-            if (quiet >= QUIET_TILES) epoch_left = EPOCH_TILES;
+            if (EPOCH && quiet >= QUIET_TILES) epoch_left = EPOCH_TILES;
             if (moved) {
                 if (uni) {
 #pragma unroll
@@ -461,7 +459,25 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_lds(const KT* __restrict__ ke
     // final synchronisation: tops include every spilled row, bins aligned
     int sp;
     synchronise(sp);
-    for (int g = tid; g < G; g += AGG_BLOCK) {
+    return err;
+}
+
+// Low/mid cardinality: each workgroup aggregates a contiguous chunk of rows
+// over all groups and writes its partial (top, K[L]) per group.
+template <class KT, class VT, class AT, int L, int VEC>
+__global__ void __launch_bounds__(AGG_BLOCK) k_agg_lds(const KT* __restrict__ keys, const VT* __restrict__ vals,
+                                                       int64_t n, int G, int R, int64_t chunk,
+                                                       int* __restrict__ ptop, long long* __restrict__ pK,
+                                                       unsigned long long* __restrict__ spill,
+                                                       uint32_t* __restrict__ status) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ AggShared sh;
+    const int64_t c0 = (int64_t)blockIdx.x * chunk;
+    const int64_t c1 = (c0 + chunk < n) ? c0 + chunk : n;
+    const uint32_t err = aggregate_range<KT, VT, AT, L, VEC, true>(keys, vals, c0, c1, G, R, smem, sh, spill);
+    const long long* bins = reinterpret_cast<const long long*>(smem);
+    const int2* TOP = reinterpret_cast<const int2*>(bins + (size_t)(G + 1) * R * L);
+    for (int g = threadIdx.x; g < G; g += AGG_BLOCK) {
         ptop[(size_t)blockIdx.x * G + g] = TOP[g].x;
 #pragma unroll
         for (int l = 0; l < L; ++l) {
@@ -476,6 +492,262 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_lds(const KT* __restrict__ ke
 // Zeroes the spill array before an aggregation pass.
 __global__ void __launch_bounds__(256) k_zero(unsigned long long* __restrict__ p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = 0;
+}
+
+// ------------------------------------------------- high cardinality path
+//
+// When the groups do not fit one workgroup's LDS, the rows are first
+// partitioned on the high bits of the key (ParallelPartition of Alg. 3,
+// Sec. V-B) into F partitions of at most GP = 2^gp_shift groups, then every
+// partition is aggregated in LDS by the same hot loop (per-tile mode: the
+// groups are many and their rows few), and partitions split over several
+// workgroups are merged (the merge phase of Alg. 3).  The order of rows
+// inside a partition is not deterministic and needs not be: level sums are
+// exact.
+//
+//   k_part_hist     per-workgroup histogram of partition ids -> counts[w][p]
+//   k_part_offsets  per partition: rows before workgroup w (rel[w][p]), size
+//   k_part_plan     partition bases, chunking into work items, work table
+//   k_part_scatter  (local key, value) pairs into their partition's range
+//   k_agg_part      one work item = one chunk of one partition, aggregated in
+//                   LDS; single-chunk partitions merge into the states
+//                   directly, others write a partial per work item
+//   k_merge_part    folds the partials of split partitions into the states
+constexpr int PART_BLOCK = 1024;
+constexpr int PART_WG = 256;                  // histogram/scatter workgroups
+constexpr int64_t PART_CHUNK = 128 * 1024;    // rows per aggregation work item
+
+struct WorkItem {
+    int p;        // partition
+    int nchunks;  // work items of this partition
+    int first;    // its first work item
+    int pad;
+    long long r0, r1;  // rows in the partitioned arrays
+};
+
+template <class KT>
+__global__ void __launch_bounds__(PART_BLOCK) k_part_hist(const KT* __restrict__ keys, int64_t n, int64_t G,
+                                                          int gp_shift, int F, int64_t chunk,
+                                                          int* __restrict__ counts) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    int* h = reinterpret_cast<int*>(smem);
+    for (int i = threadIdx.x; i < F; i += PART_BLOCK) h[i] = 0;
+    __syncthreads();
+    const int64_t c0 = (int64_t)blockIdx.x * chunk;
+    const int64_t c1 = min(n, c0 + chunk);
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += PART_BLOCK) {
+        const int64_t key = (int64_t)keys[i];
+        if ((uint64_t)key < (uint64_t)G) atomicAdd(&h[(int)(key >> gp_shift)], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < F; i += PART_BLOCK) counts[(size_t)blockIdx.x * F + i] = h[i];
+}
+
+// block per partition, one thread per histogram workgroup (blockDim = nw)
+__global__ void __launch_bounds__(PART_WG) k_part_offsets(const int* __restrict__ counts, int nw, int F,
+                                                          int* __restrict__ rel, long long* __restrict__ size) {
+    __shared__ int s[PART_WG];
+    const int p = blockIdx.x, w = threadIdx.x;
+    const int c = (w < nw) ? counts[(size_t)w * F + p] : 0;
+    s[w] = c;
+    __syncthreads();
+    // inclusive scan (Hillis-Steele) over the workgroups
+    for (int o = 1; o < PART_WG; o <<= 1) {
+        const int x = (w >= o) ? s[w - o] : 0;
+        __syncthreads();
+        s[w] += x;
+        __syncthreads();
+    }
+    if (w < nw) rel[(size_t)w * F + p] = s[w] - c;
+    if (w == PART_WG - 1) size[p] = s[w];
+}
+
+// single block: exclusive scans over the partitions (bases, work items)
+__global__ void __launch_bounds__(PART_BLOCK) k_part_plan(const long long* __restrict__ size, int F, int64_t chunk,
+                                                          long long* __restrict__ base, int* __restrict__ wfirst,
+                                                          WorkItem* __restrict__ items, int* __restrict__ nitems) {
+    __shared__ long long sb[PART_BLOCK];
+    __shared__ int sw[PART_BLOCK];
+    const int t = threadIdx.x;
+    const int per = (F + PART_BLOCK - 1) / PART_BLOCK;  // partitions per thread
+    const int p0 = min(F, t * per), p1 = min(F, p0 + per);
+    long long rs = 0;
+    int ws = 0;
+    for (int p = p0; p < p1; ++p) {
+        rs += size[p];
+        ws += (int)((size[p] + chunk - 1) / chunk);
+    }
+    sb[t] = rs;
+    sw[t] = ws;
+    __syncthreads();
+    for (int o = 1; o < PART_BLOCK; o <<= 1) {
+        const long long x = (t >= o) ? sb[t - o] : 0;
+        const int y = (t >= o) ? sw[t - o] : 0;
+        __syncthreads();
+        sb[t] += x;
+        sw[t] += y;
+        __syncthreads();
+    }
+    long long b = sb[t] - rs;
+    int wi = sw[t] - ws;
+    for (int p = p0; p < p1; ++p) {
+        const long long sz = size[p];
+        const int nc = (int)((sz + chunk - 1) / chunk);
+        base[p] = b;
+        wfirst[p] = wi;
+        for (int c = 0; c < nc; ++c) {
+            WorkItem it;
+            it.p = p;
+            it.nchunks = nc;
+            it.first = wi;
+            it.pad = 0;
+            it.r0 = b + (long long)c * chunk;
+            it.r1 = min(b + sz, it.r0 + chunk);
+            items[wi + c] = it;
+        }
+        b += sz;
+        wi += nc;
+    }
+    if (t == PART_BLOCK - 1) *nitems = sw[t];
+}
+
+template <class KT, class VT>
+__global__ void __launch_bounds__(PART_BLOCK) k_part_scatter(const KT* __restrict__ keys, const VT* __restrict__ vals,
+                                                             int64_t n, int64_t G, int gp_shift, int F, int64_t chunk,
+                                                             const long long* __restrict__ base,
+                                                             const int* __restrict__ rel,
+                                                             uint16_t* __restrict__ lkey, VT* __restrict__ lval,
+                                                             uint32_t* __restrict__ status) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    long long* cur = reinterpret_cast<long long*>(smem);
+    for (int i = threadIdx.x; i < F; i += PART_BLOCK) cur[i] = base[i] + rel[(size_t)blockIdx.x * F + i];
+    __syncthreads();
+    const int64_t c0 = (int64_t)blockIdx.x * chunk;
+    const int64_t c1 = min(n, c0 + chunk);
+    const uint32_t gmask = (1u << gp_shift) - 1;
+    bool badkey = false;
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += PART_BLOCK) {
+        const int64_t key = (int64_t)keys[i];
+        if ((uint64_t)key < (uint64_t)G) {
+            const long long slot = atomicAdd((unsigned long long*)&cur[(int)(key >> gp_shift)], 1ull);
+            lkey[slot] = (uint16_t)((uint32_t)key & gmask);
+            lval[slot] = vals[i];
+        } else {
+            badkey = true;
+        }
+    }
+    report(status, badkey ? ERR_KEY : 0u);
+}
+
+// Folds a workgroup's aligned LDS bins of group g (top `top`) and, if
+// given, the caller's state of that group into a canonical state.
+template <class AT, int L>
+__device__ __forceinline__ void fold_into_state(const long long* K, int top, AT* __restrict__ S,
+                                                long long* __restrict__ C, int64_t G, int64_t g) {
+    typedef Fmt<AT> F;
+    constexpr int c = F::CARRY;
+    const int ts = state_top(S[g]);
+    const int J = max(top, ts);
+    long long hi[L], lo[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const int ls = l - (J - ts), lk = l - (J - top);
+        hi[l] = (ls >= 0) ? C[(size_t)ls * G + g] : 0;
+        lo[l] = (ls >= 0) ? state_lo(S[(size_t)ls * G + g]) : 0;
+        long long x = 0;
+#pragma unroll
+        for (int q = 0; q < L; ++q) x = (q == lk) ? K[q] : x;
+        hi[l] += x >> c;
+        lo[l] += x & ((1ll << c) - 1);
+    }
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        long long cc, oo;
+        normalise<AT>(hi[l], lo[l], &cc, &oo);
+        S[(size_t)l * G + g] = make_S((AT*)0, F::B + (J - l) * F::W, oo);
+        C[(size_t)l * G + g] = cc;
+    }
+}
+
+template <class VT, class AT, int L>
+__global__ void __launch_bounds__(AGG_BLOCK) k_agg_part(const uint16_t* __restrict__ lkey, const VT* __restrict__ lval,
+                                                        const WorkItem* __restrict__ items,
+                                                        const int* __restrict__ nitems, int64_t G, int gp_shift,
+                                                        int* __restrict__ ptop, long long* __restrict__ pK,
+                                                        AT* __restrict__ S, long long* __restrict__ C,
+                                                        uint32_t* __restrict__ status) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ AggShared sh;
+    if ((int)blockIdx.x >= *nitems) return;  // uniform: the grid is an upper bound
+    const WorkItem it = items[blockIdx.x];
+    const int GP = 1 << gp_shift;
+    const int64_t g0 = (int64_t)it.p << gp_shift;
+    const int Gp = (int)min((int64_t)GP, G - g0);
+    const uint32_t err =
+        aggregate_range<uint16_t, VT, AT, L, 1, false>(lkey, lval, it.r0, it.r1, Gp, 1, smem, sh, nullptr);
+    const long long* bins = reinterpret_cast<const long long*>(smem);
+    const int2* TOP = reinterpret_cast<const int2*>(bins + (size_t)(Gp + 1) * L);
+    if (it.nchunks == 1) {
+        for (int g = threadIdx.x; g < Gp; g += AGG_BLOCK) fold_into_state<AT, L>(bins + (size_t)g * L, TOP[g].x, S, C, G, g0 + g);
+    } else {
+        for (int g = threadIdx.x; g < Gp; g += AGG_BLOCK) {
+            ptop[(size_t)blockIdx.x * GP + g] = TOP[g].x;
+#pragma unroll
+            for (int l = 0; l < L; ++l) pK[((size_t)blockIdx.x * L + l) * GP + g] = bins[(size_t)g * L + l];
+        }
+    }
+    report(status, err);
+}
+
+// one thread per group of a split partition: fold its work items' partials
+template <class AT, int L>
+__global__ void __launch_bounds__(256) k_merge_part(const WorkItem* __restrict__ items, const int* __restrict__ nitems,
+                                                    const int* __restrict__ wfirst, int F, int64_t G, int gp_shift,
+                                                    const int* __restrict__ ptop, const long long* __restrict__ pK,
+                                                    AT* __restrict__ S, long long* __restrict__ C) {
+    typedef Fmt<AT> F_;
+    constexpr int c = F_::CARRY;
+    const int GP = 1 << gp_shift;
+    const int p = blockIdx.y;
+    const int gl = blockIdx.x * 256 + threadIdx.x;
+    if (p >= F || gl >= GP) return;
+    const int w0 = wfirst[p];
+    if (w0 >= *nitems) return;  // empty partition (trailing)
+    const WorkItem it = items[w0];
+    if (it.p != p || it.nchunks < 2) return;  // empty or already folded
+    const int64_t g = ((int64_t)p << gp_shift) + gl;
+    if (g >= G) return;
+    const int ts = state_top(S[g]);
+    int J = ts;
+    for (int w = w0; w < w0 + it.nchunks; ++w) J = max(J, ptop[(size_t)w * GP + gl]);
+    long long hi[L], lo[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const int ls = l - (J - ts);
+        hi[l] = (ls >= 0) ? C[(size_t)ls * G + g] : 0;
+        lo[l] = (ls >= 0) ? state_lo(S[(size_t)ls * G + g]) : 0;
+    }
+    for (int w = w0; w < w0 + it.nchunks; ++w) {
+        const int d = J - ptop[(size_t)w * GP + gl];
+        long long x[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) x[l] = pK[((size_t)w * L + l) * GP + gl];
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            long long v = 0;
+#pragma unroll
+            for (int q = 0; q < L; ++q) v = (q == l - d) ? x[q] : v;
+            hi[l] += v >> c;
+            lo[l] += v & ((1ll << c) - 1);
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        long long cc, oo;
+        normalise<AT>(hi[l], lo[l], &cc, &oo);
+        S[(size_t)l * G + g] = make_S((AT*)0, F_::B + (J - l) * F_::W, oo);
+        C[(size_t)l * G + g] = cc;
+    }
 }
 
 // ------------------------------------------------------------- merging
@@ -786,7 +1058,13 @@ inline int merge_pb(int nwg, int G) {
 }
 
 struct Plan {
-    int path;       // 1: LDS bins
+    int path;       // 1: LDS bins over all groups, 2: partitioned
+    // path 2
+    int gp_shift, F, nw;     // groups per partition 2^gp_shift, partitions, hist/scatter workgroups
+    int64_t chunk_hs;        // rows per hist/scatter workgroup
+    int maxw;                // work items, upper bound
+    size_t o_counts, o_rel, o_size, o_base, o_wfirst, o_items, o_nitems, o_lkey, o_lval, o_ptop, o_pK;
+    size_t lds_agg2;         // LDS of k_agg_part
     int nwg;        // aggregate workgroups
     int64_t chunk;  // rows per workgroup (multiple of the tile)
     int R;          // LDS bin replicas
@@ -808,10 +1086,45 @@ int replicas_for(int64_t G, int L) {
     return R;
 }
 
-bool make_plan(int64_t n, int64_t G, int L, int jmax, Plan* p) {
+// High cardinality: partition, then aggregate every partition in LDS.
+bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
+    p->path = 2;
+    int s = 12;
+    while (s > 6 && ((size_t)(1 << s) + 1) * (8 * L + 12) + 512 > LDS_BIN_BUDGET) --s;
+    p->gp_shift = s;
+    const int64_t F = (G + (1 << s) - 1) >> s;
+    if (F > 16384) return false;  // histogram and cursors in LDS
+    p->F = (int)F;
+    int64_t nw = (n + (int64_t)PART_BLOCK * 16 - 1) / ((int64_t)PART_BLOCK * 16);
+    nw = std::max<int64_t>(1, std::min<int64_t>(PART_WG, nw));
+    p->nw = (int)nw;
+    p->chunk_hs = std::max<int64_t>(1, (n + nw - 1) / nw);
+    const int64_t maxw = F + (n + PART_CHUNK - 1) / PART_CHUNK;
+    if (maxw > INT32_MAX / 2) return false;
+    p->maxw = (int)maxw;
+    p->lds_agg2 = ((size_t)(1 << s) + 1) * (8 * L + 12);
+    const int GP = 1 << s;
+    size_t ws = 0;
+    auto take = [&](size_t bytes) { size_t o = ws; ws += align_up(bytes, 256); return o; };
+    p->o_counts = take((size_t)nw * F * 4);
+    p->o_rel = take((size_t)nw * F * 4);
+    p->o_size = take((size_t)F * 8);
+    p->o_base = take((size_t)F * 8);
+    p->o_wfirst = take((size_t)F * 4);
+    p->o_items = take((size_t)maxw * sizeof(WorkItem));
+    p->o_nitems = take(4);
+    p->o_lkey = take((size_t)n * 2);
+    p->o_lval = take((size_t)n * vsize);
+    p->o_ptop = take((size_t)maxw * GP * 4);
+    p->o_pK = take((size_t)maxw * GP * L * 8);
+    p->ws = ws;
+    return true;
+}
+
+bool make_plan(int64_t n, int64_t G, int L, int jmax, size_t vsize, Plan* p) {
     memset(p, 0, sizeof(*p));
     const size_t lds1 = (size_t)(G + 1) * L * 8 + (size_t)(G + 1) * 12;
-    if (lds1 > LDS_BIN_BUDGET) return false;  // high cardinality: not on this path
+    if (lds1 > LDS_BIN_BUDGET) return make_plan_part(n, G, L, vsize, p);
     p->path = 1;
     p->R = replicas_for(G, L);
     p->lds = (size_t)(G + 1) * L * 8 * p->R + (size_t)(G + 1) * 12;
@@ -865,9 +1178,64 @@ int run_merge(const Plan& p, int G, unsigned char* ws, AT* S, long long* C, hipS
     return REPRO_OK;
 }
 
+// Dynamic LDS beyond 64 KiB must be allowed per kernel on gfx950.
+inline bool allow_lds(const void* fn, size_t bytes) {
+    if (bytes <= 64 * 1024) return true;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+}
+
 template <class KT, class VT, class AT, int L>
-int run_groupby(const void* keys, const void* values, int64_t n, int G, void* states, void* workspace,
+int run_groupby_part(const void* keys, const void* values, int64_t n, int64_t G, void* states, void* workspace,
+                     uint32_t* status, const Plan& p, hipStream_t st) {
+    unsigned char* ws = static_cast<unsigned char*>(workspace);
+    const KT* k = static_cast<const KT*>(keys);
+    const VT* v = static_cast<const VT*>(values);
+    int* counts = reinterpret_cast<int*>(ws + p.o_counts);
+    int* rel = reinterpret_cast<int*>(ws + p.o_rel);
+    long long* size = reinterpret_cast<long long*>(ws + p.o_size);
+    long long* base = reinterpret_cast<long long*>(ws + p.o_base);
+    int* wfirst = reinterpret_cast<int*>(ws + p.o_wfirst);
+    WorkItem* items = reinterpret_cast<WorkItem*>(ws + p.o_items);
+    int* nitems = reinterpret_cast<int*>(ws + p.o_nitems);
+    uint16_t* lkey = reinterpret_cast<uint16_t*>(ws + p.o_lkey);
+    VT* lval = reinterpret_cast<VT*>(ws + p.o_lval);
+    int* ptop = reinterpret_cast<int*>(ws + p.o_ptop);
+    long long* pK = reinterpret_cast<long long*>(ws + p.o_pK);
+    AT* S = static_cast<AT*>(states);
+    long long* C =
+        reinterpret_cast<long long*>(static_cast<unsigned char*>(states) + align_up((size_t)G * L * sizeof(AT), 8));
+    const size_t lds_h = (size_t)p.F * 4, lds_s = (size_t)p.F * 8;
+    if (!allow_lds((const void*)k_part_hist<KT>, lds_h) || !allow_lds((const void*)k_part_scatter<KT, VT>, lds_s) ||
+        !allow_lds((const void*)k_agg_part<VT, AT, L>, p.lds_agg2))
+        return REPRO_EHIP;
+    hipLaunchKernelGGL(k_part_hist<KT>, dim3(p.nw), dim3(PART_BLOCK), lds_h, st, k, n, G, p.gp_shift, p.F, p.chunk_hs,
+                       counts);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_part_offsets, dim3(p.F), dim3(PART_WG), 0, st, counts, p.nw, p.F, rel, size);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_part_plan, dim3(1), dim3(PART_BLOCK), 0, st, size, p.F, PART_CHUNK, base, wfirst, items,
+                       nitems);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_part_scatter<KT, VT>), dim3(p.nw), dim3(PART_BLOCK), lds_s, st, k, v, n, G, p.gp_shift, p.F,
+                       p.chunk_hs, base, rel, lkey, lval, status);
+    LAUNCH_CHECK();
+    prof_before(st);
+    hipLaunchKernelGGL((k_agg_part<VT, AT, L>), dim3(p.maxw), dim3(AGG_BLOCK), p.lds_agg2, st, lkey, lval, items,
+                       nitems, G, p.gp_shift, ptop, pK, S, C, status);
+    LAUNCH_CHECK();
+    prof_after(st);
+    const int GP = 1 << p.gp_shift;
+    hipLaunchKernelGGL((k_merge_part<AT, L>), dim3((GP + 255) / 256, p.F), dim3(256), 0, st, items, nitems, wfirst,
+                       p.F, G, p.gp_shift, ptop, pK, S, C);
+    LAUNCH_CHECK();
+    return REPRO_OK;
+}
+
+template <class KT, class VT, class AT, int L>
+int run_groupby(const void* keys, const void* values, int64_t n, int64_t G64, void* states, void* workspace,
                 uint32_t* status, const Plan& p, hipStream_t st) {
+    if (p.path == 2) return run_groupby_part<KT, VT, AT, L>(keys, values, n, G64, states, workspace, status, p, st);
+    const int G = (int)G64;
     unsigned char* ws = static_cast<unsigned char*>(workspace);
     int* ptop = reinterpret_cast<int*>(ws);
     long long* pK = reinterpret_cast<long long*>(ws + align_up((size_t)p.nwg * G * 4, 256));
@@ -875,6 +1243,9 @@ int run_groupby(const void* keys, const void* values, int64_t n, int G, void* st
     const VT* v = static_cast<const VT*>(values);
     constexpr int VEC = 16 / sizeof(VT);
     const bool aligned = ((uintptr_t)k % (VEC * sizeof(KT)) == 0) && ((uintptr_t)v % 16 == 0);
+    if (!allow_lds((const void*)k_agg_lds<KT, VT, AT, L, VEC>, p.lds) ||
+        !allow_lds((const void*)k_agg_lds<KT, VT, AT, L, 1>, p.lds))
+        return REPRO_EHIP;
     unsigned long long* spill = reinterpret_cast<unsigned long long*>(ws + p.spill_off);
     hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(1024, (p.spill_words + 255) / 256)), dim3(256), 0, st,
                        spill, p.spill_words);
@@ -895,7 +1266,7 @@ int run_groupby(const void* keys, const void* values, int64_t n, int G, void* st
 }
 
 template <class KT, class VT, class AT>
-int dispatch_L(int L, const void* keys, const void* values, int64_t n, int G, void* states, void* ws,
+int dispatch_L(int L, const void* keys, const void* values, int64_t n, int64_t G, void* states, void* ws,
                uint32_t* status, const Plan& p, hipStream_t st) {
     switch (L) {
         case 1: return run_groupby<KT, VT, AT, 1>(keys, values, n, G, states, ws, status, p, st);
@@ -907,7 +1278,7 @@ int dispatch_L(int L, const void* keys, const void* values, int64_t n, int G, vo
 }
 
 template <class KT>
-int dispatch_types(repro_scalar_t vt, repro_scalar_t T, int L, const void* keys, const void* values, int64_t n, int G,
+int dispatch_types(repro_scalar_t vt, repro_scalar_t T, int L, const void* keys, const void* values, int64_t n, int64_t G,
                    void* states, void* ws, uint32_t* status, const Plan& p, hipStream_t st) {
     if (T == REPRO_F64 && vt == REPRO_F64)
         return dispatch_L<KT, double, double>(L, keys, values, n, G, states, ws, status, p, st);
@@ -1006,10 +1377,11 @@ size_t repro_state_bytes(int64_t num_groups, repro_scalar_t T, int L) {
 size_t repro_workspace_bytes(int64_t n, int64_t num_groups, repro_key_t kt, repro_scalar_t vt, repro_scalar_t T,
                              int L) {
     (void)kt;
-    (void)vt;
+    if (vt != REPRO_F32 && vt != REPRO_F64) return 0;
     Plan p;
     if (!valid_common(num_groups, T, L) || n < 0) return 0;
-    if (!make_plan(n, num_groups, L, T == REPRO_F64 ? Fmt<double>::JMAX : Fmt<float>::JMAX, &p)) return 0;
+    if (!make_plan(n, num_groups, L, T == REPRO_F64 ? Fmt<double>::JMAX : Fmt<float>::JMAX, scalar_size(vt), &p))
+        return 0;
     return p.ws;
 }
 
@@ -1027,9 +1399,10 @@ int repro_groupby_sum(const void* keys, repro_key_t kt, const void* values, repr
     if (n == 0) return REPRO_OK;
     if (!keys || !values) return REPRO_EINVAL;
     Plan p;
-    if (!make_plan(n, num_groups, L, T == REPRO_F64 ? Fmt<double>::JMAX : Fmt<float>::JMAX, &p)) return REPRO_EINVAL;
+    if (!make_plan(n, num_groups, L, T == REPRO_F64 ? Fmt<double>::JMAX : Fmt<float>::JMAX, scalar_size(vt), &p))
+        return REPRO_EINVAL;
     if (p.ws > 0 && (!workspace || workspace_bytes < p.ws || (uintptr_t)workspace % 256 != 0)) return REPRO_EINVAL;
-    const int G = (int)num_groups;
+    const int64_t G = num_groups;
     if (kt == REPRO_I32)
         return dispatch_types<int32_t>(vt, T, L, keys, values, n, G, states, workspace, status, p, stream);
     return dispatch_types<int64_t>(vt, T, L, keys, values, n, G, states, workspace, status, p, stream);

@@ -266,3 +266,60 @@ def test_tops_rising_late_use_spill_path(G, L):
     check_case(keys, vals.astype(np.float32), G, L, True, "rising tops f32 -> double")
     v32 = np.ldexp(rng.standard_normal(n), (-140 + (np.arange(n) * 250) // n)).astype(np.float32)
     check_case(keys, v32, G, L, False, "rising tops float acc")
+
+
+# ------------------------------------------------ high cardinality (partitioned)
+
+def test_highcard_config_reduced():
+    keys, vals = WL.highcard(n=2_000_000, salt=1)
+    check_case(keys, vals, 1 << 22, 2, True, "highcard reduced: Zipf int64 keys, 2^22 groups")
+
+
+def test_highcard_config_full():
+    keys, vals = WL.highcard()
+    say("case highcard full: 1e8 rows, 2^22 groups, repro<double,2>")
+    orc, ost = O.groupby_sum(keys, vals, 1 << 22, 2, True, threads=16)
+    st, status = gpu_groupby(keys, vals, 1 << 22, 2, True)
+    assert status == ost == 0
+    assert_same_states(st, orc, 1 << 22, 2, True, "highcard full")
+    out = api.finalize(st, 1 << 22, 2).cpu().numpy()
+    assert np.array_equal(out, O.finalize(orc, 1 << 22, 2))
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4])
+def test_partitioned_uniform_keys_all_levels(L):
+    rng = np.random.default_rng([21, L])
+    G, n = 100_003, 1_500_000
+    keys = rng.integers(0, G, n).astype(np.int32)
+    vals = np.ldexp(rng.standard_normal(n), rng.integers(-300, 300, n))
+    check_case(keys, vals, G, L, True, "partitioned f64")
+    v32 = np.ldexp(rng.standard_normal(n), rng.integers(-60, 60, n)).astype(np.float32)
+    check_case(keys, v32, G, L, False, "partitioned float acc")
+
+
+def test_partitioned_error_rows_and_resume():
+    rng = np.random.default_rng(33)
+    G, n = 300_000, 400_000
+    keys = rng.integers(-5, G + 5, n).astype(np.int64)
+    vals = np.ldexp(rng.standard_normal(n), rng.integers(-1000, 1010, n))
+    vals[rng.random(n) < 0.001] = np.nan
+    check_case(keys, vals, G, 3, True, "partitioned error rows")
+    # resume: two calls with a host round trip equal one call
+    orc, _ = O.groupby_sum(keys, vals, G, 3)
+    kt, vt = dev(keys), dev(vals)
+    st = api.groupby_sum(kt[:123_457], vt[:123_457], G, 3)
+    torch.cuda.synchronize()
+    st = torch.from_numpy(st.cpu().numpy().copy()).cuda()
+    st = api.groupby_sum(kt[123_457:], vt[123_457:], G, 3, states=st)
+    torch.cuda.synchronize()
+    assert_same_states(st, orc, G, 3, True, "partitioned resume")
+
+
+def test_mid_cardinality_lds_path_large_lds():
+    """Groups between the 64 KiB and 150 KiB LDS budgets stay on the LDS path."""
+    rng = np.random.default_rng(44)
+    for G, L in ((3000, 3), (5000, 2), (6000, 1)):
+        n = 1_000_000
+        keys = rng.integers(0, G, n).astype(np.int32)
+        vals = np.ldexp(rng.standard_normal(n), rng.integers(-80, 80, n))
+        check_case(keys, vals, G, L, True, "mid cardinality")
