@@ -535,9 +535,17 @@ __global__ void __launch_bounds__(PART_BLOCK) k_part_hist(const KT* __restrict__
     __syncthreads();
     const int64_t c0 = (int64_t)blockIdx.x * chunk;
     const int64_t c1 = min(n, c0 + chunk);
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += PART_BLOCK) {
-        const int64_t key = (int64_t)keys[i];
-        if ((uint64_t)key < (uint64_t)G) atomicAdd(&h[(int)(key >> gp_shift)], 1);
+    constexpr int UH = 8;  // keys in flight per thread
+    for (int64_t b = c0; b < c1; b += (int64_t)UH * PART_BLOCK) {
+        int64_t kk[UH];
+#pragma unroll
+        for (int u = 0; u < UH; ++u) {
+            const int64_t i = b + u * PART_BLOCK + threadIdx.x;
+            kk[u] = (i < c1) ? (int64_t)__builtin_nontemporal_load(&keys[i]) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < UH; ++u)
+            if ((uint64_t)kk[u] < (uint64_t)G) atomicAdd(&h[(int)(kk[u] >> gp_shift)], 1);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < F; i += PART_BLOCK) counts[(size_t)blockIdx.x * F + i] = h[i];
@@ -562,10 +570,17 @@ __global__ void __launch_bounds__(PART_WG) k_part_offsets(const int* __restrict_
     if (w == PART_WG - 1) size[p] = s[w];
 }
 
-// single block: exclusive scans over the partitions (bases, work items)
+// single block: exclusive scans over the partitions (bases, work items).
+// Every partition starts at a multiple of PART_ALIGN rows; the padding slots
+// after its rows get local key 0 and value +0.0, which contribute nothing,
+// so work items span whole aligned ranges and can use vector loads.
+constexpr int PART_ALIGN = 8;
+
+template <class VT>
 __global__ void __launch_bounds__(PART_BLOCK) k_part_plan(const long long* __restrict__ size, int F, int64_t chunk,
                                                           long long* __restrict__ base, int* __restrict__ wfirst,
-                                                          WorkItem* __restrict__ items, int* __restrict__ nitems) {
+                                                          WorkItem* __restrict__ items, int* __restrict__ nitems,
+                                                          uint16_t* __restrict__ lkey, VT* __restrict__ lval) {
     __shared__ long long sb[PART_BLOCK];
     __shared__ int sw[PART_BLOCK];
     const int t = threadIdx.x;
@@ -574,8 +589,9 @@ __global__ void __launch_bounds__(PART_BLOCK) k_part_plan(const long long* __res
     long long rs = 0;
     int ws = 0;
     for (int p = p0; p < p1; ++p) {
-        rs += size[p];
-        ws += (int)((size[p] + chunk - 1) / chunk);
+        const long long sz = (size[p] + PART_ALIGN - 1) / PART_ALIGN * PART_ALIGN;
+        rs += sz;
+        ws += (int)((sz + chunk - 1) / chunk);
     }
     sb[t] = rs;
     sw[t] = ws;
@@ -591,7 +607,11 @@ __global__ void __launch_bounds__(PART_BLOCK) k_part_plan(const long long* __res
     long long b = sb[t] - rs;
     int wi = sw[t] - ws;
     for (int p = p0; p < p1; ++p) {
-        const long long sz = size[p];
+        const long long sz = (size[p] + PART_ALIGN - 1) / PART_ALIGN * PART_ALIGN;
+        for (long long q = b + size[p]; q < b + sz; ++q) {
+            lkey[q] = 0;
+            lval[q] = (VT)0;
+        }
         const int nc = (int)((sz + chunk - 1) / chunk);
         base[p] = b;
         wfirst[p] = wi;
@@ -611,32 +631,163 @@ __global__ void __launch_bounds__(PART_BLOCK) k_part_plan(const long long* __res
     if (t == PART_BLOCK - 1) *nitems = sw[t];
 }
 
-template <class KT, class VT>
-__global__ void __launch_bounds__(PART_BLOCK) k_part_scatter(const KT* __restrict__ keys, const VT* __restrict__ vals,
-                                                             int64_t n, int64_t G, int gp_shift, int F, int64_t chunk,
-                                                             const long long* __restrict__ base,
-                                                             const int* __restrict__ rel,
-                                                             uint16_t* __restrict__ lkey, VT* __restrict__ lval,
-                                                             uint32_t* __restrict__ status) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    long long* cur = reinterpret_cast<long long*>(smem);
-    for (int i = threadIdx.x; i < F; i += PART_BLOCK) cur[i] = base[i] + rel[(size_t)blockIdx.x * F + i];
+// Exclusive scan of cnt[0..F) into off[0..F) by one 1024-thread block
+// (F <= 4096: up to 4 consecutive entries per thread, wave scans, LDS for
+// the wave totals).  Returns the total.  Contains barriers.
+__device__ __forceinline__ int block_exclusive_scan(const int* cnt, int* off, int F, int* wsum) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int per = (F + PART_BLOCK - 1) / PART_BLOCK;
+    const int p0 = min(F, t * per), p1 = min(F, p0 + per);
+    int local = 0;
+    for (int p = p0; p < p1; ++p) local += cnt[p];
+    int inc = local;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int x = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += x;
+    }
+    if (lane == 63) wsum[wave] = inc;
     __syncthreads();
+    int before = 0, total = 0;
+    for (int w = 0; w < PART_BLOCK / 64; ++w) {
+        before += (w < wave) ? wsum[w] : 0;
+        total += wsum[w];
+    }
+    int run = before + inc - local;
+    for (int p = p0; p < p1; ++p) {
+        off[p] = run;
+        run += cnt[p];
+    }
+    __syncthreads();
+    return total;
+}
+
+// Raises the byte tops[idx] to at least j.  Bytes live in 32-bit words; the
+// compare-and-swap loop ends because a byte only grows: every failed swap
+// returns a newer word, and the loop stops once the byte is >= j.
+__device__ __forceinline__ void byte_max(unsigned char* __restrict__ tops, int64_t idx, int j) {
+    unsigned int* w = reinterpret_cast<unsigned int*>(tops + (idx & ~(int64_t)3));
+    const int sh = (int)(idx & 3) * 8;
+    unsigned int old = *w;
+    while ((int)((old >> sh) & 0xFFu) < j) {
+        const unsigned int nw = (old & ~(0xFFu << sh)) | ((unsigned int)j << sh);
+        const unsigned int prev = atomicCAS(w, old, nw);
+        if (prev == old) break;
+        old = prev;
+    }
+}
+
+// Scatter of (local key, value) pairs into partitions, fused with the
+// max-exponent step: every deposited row raises its group's top, kept as one
+// byte per group (a few MiB, so it stays in L2: read first, swap only when
+// larger, so settled and hot keys cost one cached load).  The input is
+// streamed with non-temporal loads.  Each tile (RU * 1024 rows) is
+// counting-sorted by partition in LDS, then written out as contiguous
+// per-partition runs.  A row with a valid key and an
+// unusable value (NaN/Inf/out of domain) keeps its slot with value +0.0,
+// which contributes nothing; its status bit is set.
+template <class KT, class VT, class AT, int RU>
+__global__ void __launch_bounds__(PART_BLOCK)
+    k_part_scatter(const KT* __restrict__ keys, const VT* __restrict__ vals, int64_t n, int64_t G, int gp_shift, int F,
+                   int64_t chunk, const long long* __restrict__ base, const int* __restrict__ rel,
+                   uint16_t* __restrict__ lkey, VT* __restrict__ lval, unsigned char* __restrict__ gtop,
+                   uint32_t* __restrict__ status) {
+    typedef Fmt<AT> Fm;
+    constexpr int SC_TILE = RU * PART_BLOCK;  // RU rows per thread and tile
+    extern __shared__ __align__(16) unsigned char smem[];
+    long long* cur = reinterpret_cast<long long*>(smem);         // F: next global slot
+    int* cnt = reinterpret_cast<int*>(cur + F);                   // F: rows in this tile
+    int* off = cnt + F;                                           // F: tile offsets
+    VT* sv = reinterpret_cast<VT*>(off + F);                      // SC_TILE staged values
+    uint16_t* sk = reinterpret_cast<uint16_t*>(sv + SC_TILE);     // staged local keys
+    uint16_t* sp = sk + SC_TILE;                                  // staged partitions
+    __shared__ int wsum[PART_BLOCK / 64];
+    const int t = threadIdx.x;
+    for (int i = t; i < F; i += PART_BLOCK) cur[i] = base[i] + rel[(size_t)blockIdx.x * F + i];
     const int64_t c0 = (int64_t)blockIdx.x * chunk;
     const int64_t c1 = min(n, c0 + chunk);
     const uint32_t gmask = (1u << gp_shift) - 1;
-    bool badkey = false;
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += PART_BLOCK) {
-        const int64_t key = (int64_t)keys[i];
-        if ((uint64_t)key < (uint64_t)G) {
-            const long long slot = atomicAdd((unsigned long long*)&cur[(int)(key >> gp_shift)], 1ull);
-            lkey[slot] = (uint16_t)((uint32_t)key & gmask);
-            lval[slot] = vals[i];
-        } else {
-            badkey = true;
+    uint32_t err = 0;
+    for (int64_t tb = c0; tb < c1; tb += SC_TILE) {
+        for (int i = t; i < F; i += PART_BLOCK) cnt[i] = 0;
+        __syncthreads();
+        int pi[RU], rk[RU], jj[RU];
+        int64_t kk[RU];
+        uint16_t lk[RU];
+        VT vv[RU];
+        // loads first, so that the memory requests of all rows overlap
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t i = tb + u * PART_BLOCK + t;
+            kk[u] = (i < c1) ? (int64_t)__builtin_nontemporal_load(&keys[i]) : -1;
+            vv[u] = (i < c1) ? __builtin_nontemporal_load(&vals[i]) : (VT)0;
         }
+        unsigned char tt[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const bool kv = (uint64_t)kk[u] < (uint64_t)G;
+            tt[u] = gtop[kv ? kk[u] : 0];  // top filter (stays in L2)
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t i = tb + u * PART_BLOCK + t;
+            pi[u] = -1;
+            jj[u] = -1;
+            if (i < c1) {
+                const int64_t key = kk[u];
+                VT v = vv[u];
+                if ((uint64_t)key < (uint64_t)G) {
+                    const bool fin = finite_val(v);
+                    const int j = jreq_raw<AT>(frexp_raw(v));
+                    if (!fin) {
+                        err |= ERR_NONFINITE;
+                        v = (VT)0;
+                    } else if (v != (VT)0) {
+                        if (j > Fm::JMAX) {
+                            err |= ERR_RANGE;
+                            v = (VT)0;
+                        } else if (j > (int)tt[u]) {
+                            jj[u] = j;  // raise after the loop
+                        }
+                    }
+                    pi[u] = (int)(key >> gp_shift);
+                    lk[u] = (uint16_t)((uint32_t)key & gmask);
+                    vv[u] = v;
+                    rk[u] = atomicAdd(&cnt[pi[u]], 1);
+                } else {
+                    err |= ERR_KEY;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+            if (jj[u] >= 0) byte_max(gtop, kk[u], jj[u]);  // rare once tops settle
+        __syncthreads();  // all tile counts in place
+        const int ntile = block_exclusive_scan(cnt, off, F, wsum);
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            if (pi[u] >= 0) {
+                const int pos = off[pi[u]] + rk[u];
+                sv[pos] = vv[u];
+                sk[pos] = lk[u];
+                sp[pos] = (uint16_t)pi[u];
+            }
+        }
+        __syncthreads();
+        for (int j = t; j < ntile; j += PART_BLOCK) {
+            const int p = sp[j];
+            const long long slot = cur[p] + (j - off[p]);
+            lkey[slot] = sk[j];
+            lval[slot] = sv[j];
+        }
+        __syncthreads();
+        for (int i = t; i < F; i += PART_BLOCK) cur[i] += cnt[i];
     }
-    report(status, badkey ? ERR_KEY : 0u);
+    report(status, err);
+}
+
+__global__ void __launch_bounds__(256) k_fill_u32(unsigned int* __restrict__ p, int64_t n, unsigned int v) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
 }
 
 // Folds a workgroup's aligned LDS bins of group g (top `top`) and, if
@@ -669,26 +820,56 @@ __device__ __forceinline__ void fold_into_state(const long long* K, int top, AT*
     }
 }
 
+// One work item (a chunk of one partition): the final top of every group
+// of the partition is known (gtop from the scatter, and the caller's state),
+// so the bins are aligned once and rows are deposited without any raise or
+// realignment (the max-exponent-first scheme).  Values in the partitioned
+// array are finite and in the domain, or +0.0 (contributes nothing).
 template <class VT, class AT, int L>
 __global__ void __launch_bounds__(AGG_BLOCK) k_agg_part(const uint16_t* __restrict__ lkey, const VT* __restrict__ lval,
                                                         const WorkItem* __restrict__ items,
-                                                        const int* __restrict__ nitems, int64_t G, int gp_shift,
-                                                        int* __restrict__ ptop, long long* __restrict__ pK,
-                                                        AT* __restrict__ S, long long* __restrict__ C,
-                                                        uint32_t* __restrict__ status) {
+                                                        const int* __restrict__ nitems,
+                                                        const unsigned char* __restrict__ gtop,
+                                                        int64_t G, int gp_shift, int* __restrict__ ptop,
+                                                        long long* __restrict__ pK, AT* __restrict__ S,
+                                                        long long* __restrict__ C) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ AggShared sh;
     if ((int)blockIdx.x >= *nitems) return;  // uniform: the grid is an upper bound
     const WorkItem it = items[blockIdx.x];
     const int GP = 1 << gp_shift;
     const int64_t g0 = (int64_t)it.p << gp_shift;
     const int Gp = (int)min((int64_t)GP, G - g0);
-    const uint32_t err =
-        aggregate_range<uint16_t, VT, AT, L, 1, false>(lkey, lval, it.r0, it.r1, Gp, 1, smem, sh, nullptr);
-    const long long* bins = reinterpret_cast<const long long*>(smem);
-    const int2* TOP = reinterpret_cast<const int2*>(bins + (size_t)(Gp + 1) * L);
+    long long* bins = reinterpret_cast<long long*>(smem);
+    int2* TOP = reinterpret_cast<int2*>(bins + (size_t)GP * L);
+    for (int g = threadIdx.x; g < Gp; g += AGG_BLOCK) {
+        const int top = max((int)gtop[g0 + g], state_top(S[g0 + g]));
+        TOP[g] = make_int2(top, (int)extractor_hi_of((AT*)0, top));
+#pragma unroll
+        for (int l = 0; l < L; ++l) bins[(size_t)g * L + l] = 0;
+    }
+    __syncthreads();
+    // [r0, r1) is a whole number of 8-row units (aligned partitions)
+    const int64_t r0 = it.r0, r1 = it.r1;
+    constexpr int UR = PART_ALIGN;
+    for (int64_t b = r0 + (int64_t)threadIdx.x * UR; b < r1; b += (int64_t)AGG_BLOCK * UR) {
+        uint16_t g[UR];
+        VT v[UR];
+        vload<uint16_t, UR>(lkey + b, g);
+#pragma unroll
+        for (int q = 0; q < UR; q += 16 / (int)sizeof(VT)) vload<VT, 16 / sizeof(VT)>(lval + b + q, v + q);
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+            long long k[L];
+            extract_from_hi<L>((AT)v[u], (uint32_t)TOP[g[u]].y, k);
+            unsigned long long* w = reinterpret_cast<unsigned long long*>(bins + (size_t)g[u] * L);
+#pragma unroll
+            for (int l = 0; l < L; ++l) atomicAdd(w + l, (unsigned long long)k[l]);
+        }
+    }
+    __syncthreads();
     if (it.nchunks == 1) {
-        for (int g = threadIdx.x; g < Gp; g += AGG_BLOCK) fold_into_state<AT, L>(bins + (size_t)g * L, TOP[g].x, S, C, G, g0 + g);
+        for (int g = threadIdx.x; g < Gp; g += AGG_BLOCK)
+            fold_into_state<AT, L>(bins + (size_t)g * L, TOP[g].x, S, C, G, g0 + g);
     } else {
         for (int g = threadIdx.x; g < Gp; g += AGG_BLOCK) {
             ptop[(size_t)blockIdx.x * GP + g] = TOP[g].x;
@@ -696,7 +877,6 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_part(const uint16_t* __restri
             for (int l = 0; l < L; ++l) pK[((size_t)blockIdx.x * L + l) * GP + g] = bins[(size_t)g * L + l];
         }
     }
-    report(status, err);
 }
 
 // one thread per group of a split partition: fold its work items' partials
@@ -1061,6 +1241,8 @@ struct Plan {
     int path;       // 1: LDS bins over all groups, 2: partitioned
     // path 2
     int gp_shift, F, nw;     // groups per partition 2^gp_shift, partitions, hist/scatter workgroups
+    size_t o_gtop, lds_sc;   // per-group tops (one byte each), scatter LDS
+    int sc_ru;               // scatter rows per thread and tile
     int64_t chunk_hs;        // rows per hist/scatter workgroup
     int maxw;                // work items, upper bound
     size_t o_counts, o_rel, o_size, o_base, o_wfirst, o_items, o_nitems, o_lkey, o_lval, o_ptop, o_pK;
@@ -1090,19 +1272,21 @@ int replicas_for(int64_t G, int L) {
 bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
     p->path = 2;
     int s = 12;
-    while (s > 6 && ((size_t)(1 << s) + 1) * (8 * L + 12) + 512 > LDS_BIN_BUDGET) --s;
+    while (s > 6 && (size_t)(1 << s) * (8 * L + 8) + 512 > LDS_BIN_BUDGET) --s;
     p->gp_shift = s;
     const int64_t F = (G + (1 << s) - 1) >> s;
-    if (F > 16384) return false;  // histogram and cursors in LDS
+    if (F > 4096) return false;  // cursors, counts and offsets of all partitions in LDS
+    p->sc_ru = ((size_t)F * 16 + (size_t)8 * PART_BLOCK * (vsize + 4) + 512 <= LDS_BIN_BUDGET) ? 8 : 4;
+    p->lds_sc = (size_t)F * 16 + (size_t)p->sc_ru * PART_BLOCK * (vsize + 4);
     p->F = (int)F;
     int64_t nw = (n + (int64_t)PART_BLOCK * 16 - 1) / ((int64_t)PART_BLOCK * 16);
     nw = std::max<int64_t>(1, std::min<int64_t>(PART_WG, nw));
     p->nw = (int)nw;
     p->chunk_hs = std::max<int64_t>(1, (n + nw - 1) / nw);
-    const int64_t maxw = F + (n + PART_CHUNK - 1) / PART_CHUNK;
+    const int64_t maxw = F + (n + (int64_t)PART_ALIGN * F + PART_CHUNK - 1) / PART_CHUNK;
     if (maxw > INT32_MAX / 2) return false;
     p->maxw = (int)maxw;
-    p->lds_agg2 = ((size_t)(1 << s) + 1) * (8 * L + 12);
+    p->lds_agg2 = (size_t)(1 << s) * (8 * L + 8);
     const int GP = 1 << s;
     size_t ws = 0;
     auto take = [&](size_t bytes) { size_t o = ws; ws += align_up(bytes, 256); return o; };
@@ -1113,10 +1297,12 @@ bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
     p->o_wfirst = take((size_t)F * 4);
     p->o_items = take((size_t)maxw * sizeof(WorkItem));
     p->o_nitems = take(4);
-    p->o_lkey = take((size_t)n * 2);
-    p->o_lval = take((size_t)n * vsize);
+    const size_t rows_pad = (size_t)n + (size_t)PART_ALIGN * F;  // partitions padded to 8 rows
+    p->o_lkey = take(rows_pad * 2);
+    p->o_lval = take(rows_pad * vsize);
     p->o_ptop = take((size_t)maxw * GP * 4);
     p->o_pK = take((size_t)maxw * GP * L * 8);
+    p->o_gtop = take(align_up((size_t)G, 4));
     p->ws = ws;
     return true;
 }
@@ -1204,24 +1390,34 @@ int run_groupby_part(const void* keys, const void* values, int64_t n, int64_t G,
     AT* S = static_cast<AT*>(states);
     long long* C =
         reinterpret_cast<long long*>(static_cast<unsigned char*>(states) + align_up((size_t)G * L * sizeof(AT), 8));
-    const size_t lds_h = (size_t)p.F * 4, lds_s = (size_t)p.F * 8;
-    if (!allow_lds((const void*)k_part_hist<KT>, lds_h) || !allow_lds((const void*)k_part_scatter<KT, VT>, lds_s) ||
+    unsigned char* gtop = ws + p.o_gtop;
+    const size_t lds_h = (size_t)p.F * 4;
+    const void* scatter = p.sc_ru == 8 ? (const void*)k_part_scatter<KT, VT, AT, 8> : (const void*)k_part_scatter<KT, VT, AT, 4>;
+    if (!allow_lds((const void*)k_part_hist<KT>, lds_h) || !allow_lds(scatter, p.lds_sc) ||
         !allow_lds((const void*)k_agg_part<VT, AT, L>, p.lds_agg2))
         return REPRO_EHIP;
+    const int64_t nw32 = (G + 3) / 4;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(2048, (nw32 + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<unsigned int*>(gtop), nw32, 0x01010101u * (unsigned)(L - 1));
+    LAUNCH_CHECK();
     hipLaunchKernelGGL(k_part_hist<KT>, dim3(p.nw), dim3(PART_BLOCK), lds_h, st, k, n, G, p.gp_shift, p.F, p.chunk_hs,
                        counts);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_part_offsets, dim3(p.F), dim3(PART_WG), 0, st, counts, p.nw, p.F, rel, size);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_part_plan, dim3(1), dim3(PART_BLOCK), 0, st, size, p.F, PART_CHUNK, base, wfirst, items,
-                       nitems);
+    hipLaunchKernelGGL(k_part_plan<VT>, dim3(1), dim3(PART_BLOCK), 0, st, size, p.F, PART_CHUNK, base, wfirst, items,
+                       nitems, lkey, lval);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_part_scatter<KT, VT>), dim3(p.nw), dim3(PART_BLOCK), lds_s, st, k, v, n, G, p.gp_shift, p.F,
-                       p.chunk_hs, base, rel, lkey, lval, status);
+    if (p.sc_ru == 8)
+        hipLaunchKernelGGL((k_part_scatter<KT, VT, AT, 8>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k, v, n, G,
+                           p.gp_shift, p.F, p.chunk_hs, base, rel, lkey, lval, gtop, status);
+    else
+        hipLaunchKernelGGL((k_part_scatter<KT, VT, AT, 4>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k, v, n, G,
+                           p.gp_shift, p.F, p.chunk_hs, base, rel, lkey, lval, gtop, status);
     LAUNCH_CHECK();
     prof_before(st);
     hipLaunchKernelGGL((k_agg_part<VT, AT, L>), dim3(p.maxw), dim3(AGG_BLOCK), p.lds_agg2, st, lkey, lval, items,
-                       nitems, G, p.gp_shift, ptop, pK, S, C, status);
+                       nitems, gtop, G, p.gp_shift, ptop, pK, S, C);
     LAUNCH_CHECK();
     prof_after(st);
     const int GP = 1 << p.gp_shift;

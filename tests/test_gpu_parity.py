@@ -323,3 +323,12 @@ def test_mid_cardinality_lds_path_large_lds():
         keys = rng.integers(0, G, n).astype(np.int32)
         vals = np.ldexp(rng.standard_normal(n), rng.integers(-80, 80, n))
         check_case(keys, vals, G, L, True, "mid cardinality")
+
+
+def test_partitioned_many_partitions_small_tiles():
+    """Thousands of partitions (the scatter falls back to 4096-row tiles)."""
+    rng = np.random.default_rng(55)
+    G, n = 7_000_000, 1_000_000
+    keys = rng.integers(0, G, n).astype(np.int64)
+    vals = np.ldexp(rng.standard_normal(n), rng.integers(-100, 100, n))
+    check_case(keys, vals, G, 4, True, "7M groups, L=4")
