@@ -7,7 +7,7 @@
  * Aggregation in RDBMSs" (arXiv 1802.09883).  The problem statement is
  * Sec. II-A (GroupBy turns <key,value> pairs into <key,aggregate> pairs; the
  * aggregate must have the same bits for every execution); the accumulator is
- * the repro<ScalarT,L> type of Sec. IV, built on RSum (Sec. III-C, Alg. 1)
+ * the repro<ScalarT,L> type of Sec. IV, built on RSum (Sec. III-C, Alg. 2)
  * with its operator+=(ScalarT), operator+=(repro), resumable state and the
  * finalisation equation of Sec. III-C.
  *
@@ -76,14 +76,14 @@ size_t repro_state_bytes(int64_t num_groups, repro_scalar_t T, int L);
 size_t repro_workspace_bytes(int64_t n, int64_t num_groups, repro_key_t kt, repro_scalar_t vt,
                              repro_scalar_t T, int L);
 
-/* Writes the empty state of every group (the initialised state Alg. 1 loads). */
+/* Writes the empty state of every group (the initialised state Alg. 2 loads). */
 int repro_state_init(void* states, int64_t num_groups, repro_scalar_t T, int L, hipStream_t stream);
 
 /*
  * GroupBy-SUM (Sec. II-A; the repro type's operator+=(ScalarT), Sec. IV):
  * adds rows i = 0..n-1, value values[i] into group keys[i], to `states`
  * (accumulated into: pass freshly initialised states for a plain GroupBy,
- * or earlier results to resume, as Alg. 1's load/store of state allows).
+ * or earlier results to resume, as Alg. 2's load/store of state allows).
  *
  *   keys       int32 or int64 (kt), dense group ids in [0, num_groups)
  *              (identity hashing, Sec. VI-A); others set REPRO_ERR_KEY.
@@ -108,7 +108,7 @@ int repro_groupby_sum(const void* keys, repro_key_t kt, const void* values, repr
 
 /*
  * dst[g] += src[g] for every group (operator+=(repro), Sec. IV; the merge
- * phase of Alg. 3, Sec. V-B): the larger top wins, the other state's levels
+ * phase of Alg. 4, Sec. V-B): the larger top wins, the other state's levels
  * move down by the difference (its lowest levels drop off), level sums add
  * exactly, carries renormalise.  dst and src may not overlap.
  */

@@ -15,13 +15,13 @@
  * Aggregation in RDBMSs" (arXiv 1802.09883).  Sections cited below:
  *   Sec. II-B   floating-point numbers, ufp/ulp
  *   Sec. III-B  error-free transformation (EFT)
- *   Sec. III-C  RSum, Alg. 1 (levels, extractors, carry bits, finalisation
+ *   Sec. III-C  RSum, Alg. 2 (levels, extractors, carry bits, finalisation
  *               equation)
  *   Sec. IV     the repro<ScalarT,L> type and its operator+=(repro)
  *
  * Readings taken where the paper is silent or ambiguous (each one is listed
  * with its justification in the design notes of the repository):
- *   (R1) a level shift is needed when |b| >= 2^(W-1) * ulp(S^(1)) (Alg. 1);
+ *   (R1) a level shift is needed when |b| >= 2^(W-1) * ulp(S^(1)) (Alg. 2);
  *   (R2) the contribution at a level is round-half-even of r / g, the same
  *        for every state (extracting with the constant 1.5*2^E);
  *   (R3) extractor exponents sit on a fixed lattice E_j = B + j*W with
@@ -34,7 +34,7 @@
  *
  * Parity status: every function here is pinned by tests against the paper's
  * worked examples, closed forms, invariants and an independent exact
- * big-integer model of the one-pass algorithm (Alg. 1).  The absolute bit
+ * big-integer model of the one-pass algorithm (Alg. 2).  The absolute bit
  * pattern on general IEEE inputs follows from readings R1-R8.
  */
 #include <math.h>
@@ -92,7 +92,7 @@ static int lattice_E(const orc_fmt* f, int j) { return f->B + j * f->W; }
 /*
  * Smallest lattice index j whose top-level extractor can take b, i.e. the
  * smallest j with |b| < 2^(W-1) * ulp(1.5 * 2^E_j) = 2^(W-1+E_j-m)
- * (the level-shift test of Alg. 1, reading R1).  With |b| < 2^(e+1) this is
+ * (the level-shift test of Alg. 2, reading R1).  With |b| < 2^(e+1) this is
  * E_j >= e + m - W + 2.
  */
 static int orc_jreq_fmt(double b, const orc_fmt* f)
@@ -309,7 +309,7 @@ static int groupby_fresh(const void* keys, int key64, const void* vals, int val6
 }
 
 /*
- * operator+=(repro) (Sec. IV, and the merge step of Alg. 3): the combined
+ * operator+=(repro) (Sec. IV, and the merge step of Alg. 4): the combined
  * top is the larger one; the levels of the other state move down by the
  * difference (its lowest levels fall off), then level sums add exactly.
  */
@@ -341,7 +341,7 @@ int orc_merge(void* dst, const void* src, int64_t G, int T64, int L)
 
 /*
  * Accumulate rows into existing canonical states (the resumable form of
- * Alg. 1: load state, add values, store state).  Defined as the merge of
+ * Alg. 2: load state, add values, store state).  Defined as the merge of
  * the existing states with the states of the new rows alone.
  */
 int orc_groupby_sum(const void* keys, int key64, const void* vals, int val64, int64_t n, int64_t G, int T64,
@@ -377,7 +377,7 @@ static void* run_job(void* p)
 
 /*
  * The same result computed on `nthreads` row chunks in parallel, then merged
- * (the thread-level parallelism of Alg. 3 with F = 1).  Bits are identical to
+ * (the thread-level parallelism of Alg. 4 with F = 1).  Bits are identical to
  * orc_groupby_sum by construction; tests check that too.
  */
 int orc_groupby_sum_threads(const void* keys, int key64, const void* vals, int val64, int64_t n, int64_t G,

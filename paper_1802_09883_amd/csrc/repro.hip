@@ -6,8 +6,8 @@
 // Hot path of repro_groupby_sum (one HBM pass over keys and values):
 //   k_agg_lds    each workgroup streams a contiguous chunk of rows in tiles;
 //                per tile: key -> group (identity hashing, Sec. VI-A), the
-//                per-group top index (max-exponent step; Alg. 1's level
-//                check done once per tile as Alg. 2 does once per block),
+//                per-group top index (max-exponent step; Alg. 2's level
+//                check done once per tile as Alg. 3 does once per block),
 //                realignment of the LDS bins of groups whose top rose,
 //                pre-rounded extraction into L integer units, exact int64
 //                adds into per-(level, group) LDS bins.  At the end the
@@ -296,7 +296,7 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
 
     // Synchronisation point: all deposits before it are done.  If a top was
     // raised since the last one, realign every group with P > TOP (its levels
-    // move down by the rise, the lowest fall off: the level shift of Alg. 1)
+    // move down by the rise, the lowest fall off: the level shift of Alg. 2)
     // and recompute whether all groups share one top.  Returns whether rows
     // went to the spill array since the last synchronisation.
     auto synchronise = [&](int& spilled) {
@@ -497,11 +497,11 @@ __global__ void __launch_bounds__(256) k_zero(unsigned long long* __restrict__ p
 // ------------------------------------------------- high cardinality path
 //
 // When the groups do not fit one workgroup's LDS, the rows are first
-// partitioned on the high bits of the key (ParallelPartition of Alg. 3,
+// partitioned on the high bits of the key (ParallelPartition of Alg. 4,
 // Sec. V-B) into F partitions of at most GP = 2^gp_shift groups, then every
 // partition is aggregated in LDS by the same hot loop (per-tile mode: the
 // groups are many and their rows few), and partitions split over several
-// workgroups are merged (the merge phase of Alg. 3).  The order of rows
+// workgroups are merged (the merge phase of Alg. 4).  The order of rows
 // inside a partition is not deterministic and needs not be: level sums are
 // exact.
 //

@@ -8,7 +8,7 @@
 // Sec. III-C).  The extractor exponents sit on the fixed lattice
 // E_j = B + j*W; a group's top index j* is the smallest lattice index whose
 // first level can take every value of the group (the level-shift test
-// |b| < 2^(W-1) ulp(S^(1)) of Alg. 1).  Units of one level add exactly, so
+// |b| < 2^(W-1) ulp(S^(1)) of Alg. 2).  Units of one level add exactly, so
 // their sum is independent of order.  The canonical state stores each
 // level as the paper's running sum S in [1.5, 1.75) * 2^E plus a carry
 // count C (Sec. III-C).

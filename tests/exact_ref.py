@@ -1,10 +1,10 @@
-"""Independent exact model of the paper's one-pass RSum (Alg. 1), in rationals.
+"""Independent exact model of the paper's one-pass RSum (Alg. 2), in rationals.
 
-Test-side only.  It follows the structure of Alg. 1 (Sec. III-C) step by step:
+Test-side only.  It follows the structure of Alg. 2 (Sec. III-C) step by step:
 running sums S^(l) and carry counts C^(l) per level, the level-shift loop when
 |b| >= 2^h * ulp(S^(1)), per-level extraction, and carry-bit propagation after
 every value; finalisation by the equation of Sec. III-C from the last level
-up.  Merging two states follows the lane merge of Alg. 2 (Sec. III-D) after
+up.  Merging two states follows the lane merge of Alg. 3 (Sec. III-D) after
 aligning the lower state with the same level-shift step.
 
 It shares no code with the C oracle, which uses the two-pass "maximum
@@ -69,13 +69,13 @@ def rne_int(x: Fraction) -> int:
 
 
 class OnePassRSum:
-    """State of Alg. 1 for one group, in exact arithmetic.
+    """State of Alg. 2 for one group, in exact arithmetic.
 
     m: fraction bits; W: level spacing; f0: exponent of the first extractor
     of a fresh state (the paper's f); h: level-shift threshold exponent
     (the text's h = W-1); tie: 'state-free' rounds r / ulp(S) half-even,
     'literal' computes (r (+) S) (-) S with one rounding to the format, the
-    literal form of Alg. 1 whose ties depend on S."""
+    literal form of Alg. 2 whose ties depend on S."""
 
     def __init__(self, m: int, W: int, f0: int, L: int, h: int | None = None, tie: str = "state-free"):
         self.m, self.W, self.L = m, W, L

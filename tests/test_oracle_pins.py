@@ -2,8 +2,8 @@
 
 Each test names the passage it follows.  The oracle (two-pass, integer level
 sums, in C) is checked against: the paper's printed worked examples (golden
-fixtures), the closed forms of Table 3, an independent exact model of the
-one-pass Alg. 1 (tests/exact_ref.py), special cases with known answers, and
+fixtures), the closed forms of Table II, an independent exact model of the
+one-pass Alg. 2 (tests/exact_ref.py), special cases with known answers, and
 Python's correctly rounded integer division.
 """
 import itertools
@@ -107,7 +107,7 @@ def test_p4_fig2_every_order(golden, m, key):
 
 
 def test_p4_literal_alg1_is_order_dependent(golden):
-    """Reading R2: Alg. 1 taken literally (ties decided by the running sum)
+    """Reading R2: Alg. 2 taken literally (ties decided by the running sum)
     does not give one result for the Fig. 2 inputs; the state-free tie rule does."""
     d = golden("fig2_rsum_example.txt")
     vals = [float(x) for x in d["values"].split()]
@@ -137,8 +137,8 @@ def test_p5_fig3_carry(golden):
 # ---------------------------------------------------------------- P6
 
 def test_p6_sql_values_every_order(golden):
-    """Alg. 0 (Sec. I): plain sums depend on the order; repro sums do not."""
-    d = golden("sql_alg0.txt")
+    """Alg. 1 (Sec. I): plain sums depend on the order; repro sums do not."""
+    d = golden("sql_alg1.txt")
     vals = [float(x) for x in d["values"].split()]
     naive = set()
     for p in itertools.permutations(vals):
@@ -158,10 +158,10 @@ def test_p6_sql_values_every_order(golden):
 
 # ---------------------------------------------------------------- P7
 
-def test_p7_table3_closed_forms(golden):
-    """Table 3 (Sec. VI-B): the printed bounds follow from the two formulas
+def test_p7_table2_closed_forms(golden):
+    """Table II (Sec. VI-B): the printed bounds follow from the two formulas
     with eps = 2^-53, W = 40, max|b| = 2 (U[1,2)) and 22 (Exp(1))."""
-    d = golden("table3_error_bounds.txt")
+    d = golden("table2_error_bounds.txt")
     eps, W = 2.0 ** -53, 40
     cols = [(1e3, 1.5, 2.0), (1e3, 1.0, 22.0), (1e6, 1.5, 2.0), (1e6, 1.0, 22.0)]
     for (n, mean, mx), printed in zip(cols, d["conv"].split()):
@@ -175,7 +175,7 @@ def test_p7_table3_closed_forms(golden):
 @pytest.mark.parametrize("dist", ["uniform12", "exp1"])
 @pytest.mark.parametrize("L", [1, 2, 3])
 def test_p7_error_within_bound(n, dist, L):
-    """Reading R9: |sum_l K_l g_l - sum b| <= n 2^((1-L)W) max|b| (the Table 3
+    """Reading R9: |sum_l K_l g_l - sum b| <= n 2^((1-L)W) max|b| (the Table II
     expression without its factor 1/2, which the lattice cannot promise)."""
     rng = np.random.default_rng([7, n, L, len(dist)])
     v = rng.uniform(1.0, 2.0, n) if dist == "uniform12" else rng.exponential(1.0, n)
@@ -292,7 +292,7 @@ def _toy_values(rng, m, n, emin_v, emax_v):
 
 def test_p11_toy_formats_match_onepass_model():
     """Every order of tiny inputs in toy formats: the oracle's two-pass form
-    equals the one-pass Alg. 1 (levels, carries and result)."""
+    equals the one-pass Alg. 2 (levels, carries and result)."""
     rng = np.random.default_rng(11)
     for trial in range(250):
         m = int(rng.integers(3, 9))
@@ -323,7 +323,7 @@ def test_p11_toy_formats_match_onepass_model():
 def test_p11_ieee_states_match_onepass_model(T64):
     """IEEE formats, wide exponent spread incl. subnormals and zeros: the
     oracle's canonical (S, C) equals the running sums and carry counts the
-    one-pass Alg. 1 ends with, for random orders; finalised values agree."""
+    one-pass Alg. 2 ends with, for random orders; finalised values agree."""
     rng = np.random.default_rng([11, T64])
     m, W, B = (52, 40, -1022) if T64 else (23, 18, -126)
     emin, emax = (-1022, 1023) if T64 else (-126, 127)
@@ -353,7 +353,7 @@ def test_p11_ieee_states_match_onepass_model(T64):
 
 def test_merge_matches_lane_merge_model():
     """operator+=(repro): the oracle's merge equals the one-pass model's
-    alignment + lane merge (Alg. 2's horizontal summation)."""
+    alignment + lane merge (Alg. 3's horizontal summation)."""
     rng = np.random.default_rng(13)
     for trial in range(150):
         L = int(rng.integers(1, 5))

@@ -2,8 +2,8 @@
 
 The aggregate of each group must have the same bits for any execution: any
 physical order of the rows, any split into chunks accumulated one after the
-other (resumable state, Alg. 1), any merge tree of partial states
-(operator+=(repro), Sec. IV; merge phase of Alg. 3) and any thread count.
+other (resumable state, Alg. 2), any merge tree of partial states
+(operator+=(repro), Sec. IV; merge phase of Alg. 4) and any thread count.
 """
 import numpy as np
 from hypothesis import given, settings, strategies as st
