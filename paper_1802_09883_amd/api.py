@@ -61,11 +61,17 @@ def state_init(num_groups: int, L: int = 2, T=torch.float64, device="cuda", stre
 _WS = {}
 
 
-def _workspace(nbytes: int, device) -> torch.Tensor:
-    key = torch.device(device)
+def _workspace(nbytes: int, device, stream=None) -> torch.Tensor:
+    """A cached workspace per (device, stream): calls on one stream are
+    ordered, so they may share it; calls on different streams get their own.
+    It is allocated on that stream, so the caching allocator does not hand its
+    memory to another stream while a kernel may still use it."""
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    key = (torch.device(device), s.cuda_stream)
     ws = _WS.get(key)
     if ws is None or ws.numel() < nbytes:
-        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        with torch.cuda.stream(s):
+            ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
         _WS[key] = ws
     return ws
 
@@ -90,7 +96,7 @@ def groupby_sum(keys: torch.Tensor, values: torch.Tensor, num_groups: int, L: in
         states = state_init(num_groups, L, T, dev, stream)
     n = keys.numel()
     need = workspace_bytes(n, num_groups, keys.dtype, values.dtype, L, T)
-    ws = workspace if workspace is not None else (_workspace(need, dev) if need else None)
+    ws = workspace if workspace is not None else (_workspace(need, dev, stream) if need else None)
     rc = lib.repro_groupby_sum(_vp(keys), _KEY[keys.dtype], _vp(values), _SCALAR[values.dtype], n, num_groups,
                                _T(T), L, _vp(states), _vp(ws), ws.numel() if ws is not None else 0, _vp(status),
                                _stream(dev, stream))

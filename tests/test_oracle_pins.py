@@ -106,7 +106,7 @@ def test_p4_fig2_every_order(golden, m, key):
         assert X.onepass_sum(perm, m, W, f, L, -20, 20) == Fraction(d[key])
 
 
-def test_p4_literal_alg1_is_order_dependent(golden):
+def test_p4_literal_running_s_ties_are_order_dependent(golden):
     """Reading R2: Alg. 2 taken literally (ties decided by the running sum)
     does not give one result for the Fig. 2 inputs; the state-free tie rule does."""
     d = golden("fig2_rsum_example.txt")
