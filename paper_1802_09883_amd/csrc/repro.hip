@@ -662,36 +662,18 @@ __device__ __forceinline__ int block_exclusive_scan(const int* cnt, int* off, in
     return total;
 }
 
-// Raises the byte tops[idx] to at least j.  Bytes live in 32-bit words; the
-// compare-and-swap loop ends because a byte only grows: every failed swap
-// returns a newer word, and the loop stops once the byte is >= j.
-__device__ __forceinline__ void byte_max(unsigned char* __restrict__ tops, int64_t idx, int j) {
-    unsigned int* w = reinterpret_cast<unsigned int*>(tops + (idx & ~(int64_t)3));
-    const int sh = (int)(idx & 3) * 8;
-    unsigned int old = *w;
-    while ((int)((old >> sh) & 0xFFu) < j) {
-        const unsigned int nw = (old & ~(0xFFu << sh)) | ((unsigned int)j << sh);
-        const unsigned int prev = atomicCAS(w, old, nw);
-        if (prev == old) break;
-        old = prev;
-    }
-}
-
-// Scatter of (local key, value) pairs into partitions, fused with the
-// max-exponent step: every deposited row raises its group's top, kept as one
-// byte per group (a few MiB, so it stays in L2: read first, swap only when
-// larger, so settled and hot keys cost one cached load).  The input is
+// Scatter of (local key, value) pairs into partitions.  The input is
 // streamed with non-temporal loads.  Each tile (RU * 1024 rows) is
 // counting-sorted by partition in LDS, then written out as contiguous
-// per-partition runs.  A row with a valid key and an
-// unusable value (NaN/Inf/out of domain) keeps its slot with value +0.0,
-// which contributes nothing; its status bit is set.
+// per-partition runs.  A row with a valid key and an unusable value
+// (NaN/Inf/out of domain) keeps its slot with value +0.0, which contributes
+// nothing; its status bit is set.  The max-exponent step is left to the
+// aggregation of each partition, where the partition's tops sit in LDS.
 template <class KT, class VT, class AT, int RU>
 __global__ void __launch_bounds__(PART_BLOCK)
     k_part_scatter(const KT* __restrict__ keys, const VT* __restrict__ vals, int64_t n, int64_t G, int gp_shift, int F,
                    int64_t chunk, const long long* __restrict__ base, const int* __restrict__ rel,
-                   uint16_t* __restrict__ lkey, VT* __restrict__ lval, unsigned char* __restrict__ gtop,
-                   uint32_t* __restrict__ status) {
+                   uint16_t* __restrict__ lkey, VT* __restrict__ lval, uint32_t* __restrict__ status) {
     typedef Fmt<AT> Fm;
     constexpr int SC_TILE = RU * PART_BLOCK;  // RU rows per thread and tile
     extern __shared__ __align__(16) unsigned char smem[];
@@ -711,7 +693,7 @@ __global__ void __launch_bounds__(PART_BLOCK)
     for (int64_t tb = c0; tb < c1; tb += SC_TILE) {
         for (int i = t; i < F; i += PART_BLOCK) cnt[i] = 0;
         __syncthreads();
-        int pi[RU], rk[RU], jj[RU];
+        int pi[RU], rk[RU];
         int64_t kk[RU];
         uint16_t lk[RU];
         VT vv[RU];
@@ -722,33 +704,20 @@ __global__ void __launch_bounds__(PART_BLOCK)
             kk[u] = (i < c1) ? (int64_t)__builtin_nontemporal_load(&keys[i]) : -1;
             vv[u] = (i < c1) ? __builtin_nontemporal_load(&vals[i]) : (VT)0;
         }
-        unsigned char tt[RU];
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const bool kv = (uint64_t)kk[u] < (uint64_t)G;
-            tt[u] = gtop[kv ? kk[u] : 0];  // top filter (stays in L2)
-        }
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const int64_t i = tb + u * PART_BLOCK + t;
             pi[u] = -1;
-            jj[u] = -1;
             if (i < c1) {
                 const int64_t key = kk[u];
                 VT v = vv[u];
                 if ((uint64_t)key < (uint64_t)G) {
-                    const bool fin = finite_val(v);
-                    const int j = jreq_raw<AT>(frexp_raw(v));
-                    if (!fin) {
+                    if (!finite_val(v)) {
                         err |= ERR_NONFINITE;
                         v = (VT)0;
-                    } else if (v != (VT)0) {
-                        if (j > Fm::JMAX) {
-                            err |= ERR_RANGE;
-                            v = (VT)0;
-                        } else if (j > (int)tt[u]) {
-                            jj[u] = j;  // raise after the loop
-                        }
+                    } else if (v != (VT)0 && jreq_raw<AT>(frexp_raw(v)) > Fm::JMAX) {
+                        err |= ERR_RANGE;
+                        v = (VT)0;
                     }
                     pi[u] = (int)(key >> gp_shift);
                     lk[u] = (uint16_t)((uint32_t)key & gmask);
@@ -759,9 +728,6 @@ __global__ void __launch_bounds__(PART_BLOCK)
                 }
             }
         }
-#pragma unroll
-        for (int u = 0; u < RU; ++u)
-            if (jj[u] >= 0) byte_max(gtop, kk[u], jj[u]);  // rare once tops settle
         __syncthreads();  // all tile counts in place
         const int ntile = block_exclusive_scan(cnt, off, F, wsum);
 #pragma unroll
@@ -784,10 +750,6 @@ __global__ void __launch_bounds__(PART_BLOCK)
         for (int i = t; i < F; i += PART_BLOCK) cur[i] += cnt[i];
     }
     report(status, err);
-}
-
-__global__ void __launch_bounds__(256) k_fill_u32(unsigned int* __restrict__ p, int64_t n, unsigned int v) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
 }
 
 // Folds a workgroup's aligned LDS bins of group g (top `top`) and, if
@@ -820,53 +782,34 @@ __device__ __forceinline__ void fold_into_state(const long long* K, int top, AT*
     }
 }
 
-// One work item (a chunk of one partition): the final top of every group
-// of the partition is known (gtop from the scatter, and the caller's state),
-// so the bins are aligned once and rows are deposited without any raise or
-// realignment (the max-exponent-first scheme).  Values in the partitioned
-// array are finite and in the domain, or +0.0 (contributes nothing).
+// One work item (a chunk of one partition): the partition's groups are
+// aggregated in LDS by the same per-tile loop as the low-cardinality kernel
+// (tops raised in LDS, bins realigned once per tile, no spill array).
+// Partitions taken by one work item fold into the caller's states directly,
+// others write a partial (top, K[L]) per group for k_merge_part.  Values in
+// the partitioned array are finite and in the domain, or +0.0 (contributes
+// nothing); rows of the padding have local key 0 and value +0.0.
 template <class VT, class AT, int L>
 __global__ void __launch_bounds__(AGG_BLOCK) k_agg_part(const uint16_t* __restrict__ lkey, const VT* __restrict__ lval,
                                                         const WorkItem* __restrict__ items,
-                                                        const int* __restrict__ nitems,
-                                                        const unsigned char* __restrict__ gtop,
-                                                        int64_t G, int gp_shift, int* __restrict__ ptop,
-                                                        long long* __restrict__ pK, AT* __restrict__ S,
-                                                        long long* __restrict__ C) {
+                                                        const int* __restrict__ nitems, int64_t G, int gp_shift,
+                                                        int* __restrict__ ptop, long long* __restrict__ pK,
+                                                        AT* __restrict__ S, long long* __restrict__ C,
+                                                        uint32_t* __restrict__ status) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ AggShared sh;
     if ((int)blockIdx.x >= *nitems) return;  // uniform: the grid is an upper bound
     const WorkItem it = items[blockIdx.x];
     const int GP = 1 << gp_shift;
     const int64_t g0 = (int64_t)it.p << gp_shift;
     const int Gp = (int)min((int64_t)GP, G - g0);
-    long long* bins = reinterpret_cast<long long*>(smem);
-    int2* TOP = reinterpret_cast<int2*>(bins + (size_t)GP * L);
-    for (int g = threadIdx.x; g < Gp; g += AGG_BLOCK) {
-        const int top = max((int)gtop[g0 + g], state_top(S[g0 + g]));
-        TOP[g] = make_int2(top, (int)extractor_hi_of((AT*)0, top));
-#pragma unroll
-        for (int l = 0; l < L; ++l) bins[(size_t)g * L + l] = 0;
-    }
-    __syncthreads();
-    // [r0, r1) is a whole number of 8-row units (aligned partitions)
-    const int64_t r0 = it.r0, r1 = it.r1;
-    constexpr int UR = PART_ALIGN;
-    for (int64_t b = r0 + (int64_t)threadIdx.x * UR; b < r1; b += (int64_t)AGG_BLOCK * UR) {
-        uint16_t g[UR];
-        VT v[UR];
-        vload<uint16_t, UR>(lkey + b, g);
-#pragma unroll
-        for (int q = 0; q < UR; q += 16 / (int)sizeof(VT)) vload<VT, 16 / sizeof(VT)>(lval + b + q, v + q);
-#pragma unroll
-        for (int u = 0; u < UR; ++u) {
-            long long k[L];
-            extract_from_hi<L>((AT)v[u], (uint32_t)TOP[g[u]].y, k);
-            unsigned long long* w = reinterpret_cast<unsigned long long*>(bins + (size_t)g[u] * L);
-#pragma unroll
-            for (int l = 0; l < L; ++l) atomicAdd(w + l, (unsigned long long)k[l]);
-        }
-    }
-    __syncthreads();
+    // [r0, r1) starts on a multiple of 8 rows (aligned partitions), so the
+    // vector loads of the tiles are aligned
+    constexpr int VEC = 16 / sizeof(VT);
+    const uint32_t err =
+        aggregate_range<uint16_t, VT, AT, L, VEC, false>(lkey, lval, it.r0, it.r1, Gp, 1, smem, sh, nullptr);
+    const long long* bins = reinterpret_cast<const long long*>(smem);
+    const int2* TOP = reinterpret_cast<const int2*>(bins + (size_t)(Gp + 1) * L);
     if (it.nchunks == 1) {
         for (int g = threadIdx.x; g < Gp; g += AGG_BLOCK)
             fold_into_state<AT, L>(bins + (size_t)g * L, TOP[g].x, S, C, G, g0 + g);
@@ -877,6 +820,7 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_part(const uint16_t* __restri
             for (int l = 0; l < L; ++l) pK[((size_t)blockIdx.x * L + l) * GP + g] = bins[(size_t)g * L + l];
         }
     }
+    report(status, err);
 }
 
 // one thread per group of a split partition: fold its work items' partials
@@ -1241,7 +1185,7 @@ struct Plan {
     int path;       // 1: LDS bins over all groups, 2: partitioned
     // path 2
     int gp_shift, F, nw;     // groups per partition 2^gp_shift, partitions, hist/scatter workgroups
-    size_t o_gtop, lds_sc;   // per-group tops (one byte each), scatter LDS
+    size_t lds_sc;           // scatter LDS
     int sc_ru;               // scatter rows per thread and tile
     int64_t chunk_hs;        // rows per hist/scatter workgroup
     int maxw;                // work items, upper bound
@@ -1272,7 +1216,7 @@ int replicas_for(int64_t G, int L) {
 bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
     p->path = 2;
     int s = 12;
-    while (s > 6 && (size_t)(1 << s) * (8 * L + 8) + 512 > LDS_BIN_BUDGET) --s;
+    while (s > 6 && ((size_t)(1 << s) + 1) * (8 * L + 12) > LDS_BIN_BUDGET) --s;
     p->gp_shift = s;
     const int64_t F = (G + (1 << s) - 1) >> s;
     if (F > 4096) return false;  // cursors, counts and offsets of all partitions in LDS
@@ -1286,7 +1230,7 @@ bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
     const int64_t maxw = F + (n + (int64_t)PART_ALIGN * F + PART_CHUNK - 1) / PART_CHUNK;
     if (maxw > INT32_MAX / 2) return false;
     p->maxw = (int)maxw;
-    p->lds_agg2 = (size_t)(1 << s) * (8 * L + 8);
+    p->lds_agg2 = ((size_t)(1 << s) + 1) * (8 * L + 12);  // bins, TOP and P of aggregate_range
     const int GP = 1 << s;
     size_t ws = 0;
     auto take = [&](size_t bytes) { size_t o = ws; ws += align_up(bytes, 256); return o; };
@@ -1302,7 +1246,6 @@ bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
     p->o_lval = take(rows_pad * vsize);
     p->o_ptop = take((size_t)maxw * GP * 4);
     p->o_pK = take((size_t)maxw * GP * L * 8);
-    p->o_gtop = take(align_up((size_t)G, 4));
     p->ws = ws;
     return true;
 }
@@ -1390,16 +1333,11 @@ int run_groupby_part(const void* keys, const void* values, int64_t n, int64_t G,
     AT* S = static_cast<AT*>(states);
     long long* C =
         reinterpret_cast<long long*>(static_cast<unsigned char*>(states) + align_up((size_t)G * L * sizeof(AT), 8));
-    unsigned char* gtop = ws + p.o_gtop;
     const size_t lds_h = (size_t)p.F * 4;
     const void* scatter = p.sc_ru == 8 ? (const void*)k_part_scatter<KT, VT, AT, 8> : (const void*)k_part_scatter<KT, VT, AT, 4>;
     if (!allow_lds((const void*)k_part_hist<KT>, lds_h) || !allow_lds(scatter, p.lds_sc) ||
         !allow_lds((const void*)k_agg_part<VT, AT, L>, p.lds_agg2))
         return REPRO_EHIP;
-    const int64_t nw32 = (G + 3) / 4;
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(2048, (nw32 + 255) / 256)), dim3(256), 0, st,
-                       reinterpret_cast<unsigned int*>(gtop), nw32, 0x01010101u * (unsigned)(L - 1));
-    LAUNCH_CHECK();
     hipLaunchKernelGGL(k_part_hist<KT>, dim3(p.nw), dim3(PART_BLOCK), lds_h, st, k, n, G, p.gp_shift, p.F, p.chunk_hs,
                        counts);
     LAUNCH_CHECK();
@@ -1410,14 +1348,14 @@ int run_groupby_part(const void* keys, const void* values, int64_t n, int64_t G,
     LAUNCH_CHECK();
     if (p.sc_ru == 8)
         hipLaunchKernelGGL((k_part_scatter<KT, VT, AT, 8>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k, v, n, G,
-                           p.gp_shift, p.F, p.chunk_hs, base, rel, lkey, lval, gtop, status);
+                           p.gp_shift, p.F, p.chunk_hs, base, rel, lkey, lval, status);
     else
         hipLaunchKernelGGL((k_part_scatter<KT, VT, AT, 4>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k, v, n, G,
-                           p.gp_shift, p.F, p.chunk_hs, base, rel, lkey, lval, gtop, status);
+                           p.gp_shift, p.F, p.chunk_hs, base, rel, lkey, lval, status);
     LAUNCH_CHECK();
     prof_before(st);
     hipLaunchKernelGGL((k_agg_part<VT, AT, L>), dim3(p.maxw), dim3(AGG_BLOCK), p.lds_agg2, st, lkey, lval, items,
-                       nitems, gtop, G, p.gp_shift, ptop, pK, S, C);
+                       nitems, G, p.gp_shift, ptop, pK, S, C, status);
     LAUNCH_CHECK();
     prof_after(st);
     const int GP = 1 << p.gp_shift;

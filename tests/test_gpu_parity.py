@@ -263,7 +263,9 @@ def test_tops_rising_late_use_spill_path(G, L):
     vals[late] = np.ldexp(rng.standard_normal(200), rng.integers(950, 1000, 200))
     keys = rng.integers(0, G, n).astype(np.int32)
     check_case(keys, vals, G, L, True, "rising tops f64")
-    check_case(keys, vals.astype(np.float32), G, L, True, "rising tops f32 -> double")
+    with np.errstate(over="ignore"):  # values beyond float's range become +-Inf: skipped rows
+        v_narrow = vals.astype(np.float32)
+    check_case(keys, v_narrow, G, L, True, "rising tops f32 -> double")
     v32 = np.ldexp(rng.standard_normal(n), (-140 + (np.arange(n) * 250) // n)).astype(np.float32)
     check_case(keys, v32, G, L, False, "rising tops float acc")
 
