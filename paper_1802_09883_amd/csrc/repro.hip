@@ -118,8 +118,12 @@ __device__ __forceinline__ void report(uint32_t* status, uint32_t err) {
 //
 // LDS layout (G real groups plus one trash slot G that absorbs skipped
 // rows, so the deposit loop has no per-row branch):
-//   bins[G+1][R][L]  int64 level sums; lane r deposits into replica r % R
-//                    (R > 1 only when groups are few, to spread contention)
+//   bins[L][G+1][R]  int64 level sums; lane r deposits into replica r % R
+//                    (R > 1 only when groups are few, to spread contention).
+//                    Level-major, so that the words one level-add of a wave
+//                    touches (random groups) spread over all LDS banks for
+//                    every L; a group-major layout with a 16- or 32-byte
+//                    group stride would use only part of the banks.
 //   TOP[G+1]         {top index, high word of the level-0 extractor}
 //   P[G+1]           pending top, raised with ds_max while a tile is read
 // A workgroup-uniform fast path applies while every group sits at the same
@@ -256,7 +260,9 @@ constexpr int QUIET_TILES = 1;   // quiet per-tile synchronisations before epoch
 // The aggregation of rows [c0, c1) into LDS by one workgroup (the hot loop
 // of both aggregation kernels).  On return the bins are aligned to every
 // group's top (TOP), and the lane's status bits are returned.  EPOCH
-// enables epoch mode, which needs the spill array.
+// enables epoch mode, which needs the spill array, and the tracking of a
+// top shared by all groups (few groups, whose tops settle early); without
+// it every tile synchronises and rows read their group's top from LDS.
 template <class KT, class VT, class AT, int L, int VEC, bool EPOCH>
 __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys, const VT* __restrict__ vals,
                                                     int64_t c0, int64_t c1, int G, int R, unsigned char* smem,
@@ -269,8 +275,9 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
 
     const int tid = threadIdx.x;
     const int rep = (tid & 63) & (R - 1);
-    const uint32_t gstride = (uint32_t)(R * L * 8);  // bytes per group in bins
-    const uint32_t lane_off = (uint32_t)(rep * L * 8);
+    const uint32_t gstride = (uint32_t)(R * 8);             // bytes per group in a level
+    const uint32_t lstride = (uint32_t)((G + 1) * R * 8);   // bytes per level
+    const uint32_t lane_off = (uint32_t)(rep * 8);
     for (int i = tid; i < (G + 1) * R * L; i += AGG_BLOCK) bins[i] = 0;
     const uint32_t h_init = extractor_hi_of((AT*)0, L - 1);
     for (int i = tid; i < G; i += AGG_BLOCK) {
@@ -315,15 +322,22 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
             int top = TOP[g].x;
             if (p > top) {
                 const int d = p - top;
+                const size_t ls = (size_t)(G + 1) * R;  // words per level
                 for (int r = 0; r < R; ++r) {
-                    long long* w = bins + ((size_t)g * R + r) * L;
+                    long long* w = bins + (size_t)g * R + r;
 #pragma unroll
-                    for (int l = L - 1; l >= 0; --l) w[l] = (l - d >= 0) ? w[l - d] : 0;
+                    for (int l = L - 1; l >= 0; --l) w[l * ls] = (l - d >= 0) ? w[(l - d) * ls] : 0;
                 }
                 TOP[g] = make_int2(p, (int)extractor_hi_of((AT*)0, p));
                 top = p;
             }
             m = max(m, top);
+        }
+        if (!EPOCH) {
+            // many groups whose tops rise at different times: no shared top
+            __syncthreads();
+            uni = false;
+            return true;
         }
         if (tid == 0) sh.cnt = 0;
         atomicMax(&sh.newmax, m);  // newmax only grows: tops never fall
@@ -434,10 +448,10 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
         for (int i = 0; i < ROWS_PER_THREAD; ++i) {
             long long k[L];
             extract_from_hi<L>((AT)vc[i], hi_[i], k);
-            unsigned long long* w =
-                reinterpret_cast<unsigned long long*>(smem + __umul24((uint32_t)gi[i], gstride) + lane_off);
+            unsigned char* w = smem + __umul24((uint32_t)gi[i], gstride) + lane_off;
 #pragma unroll
-            for (int l = 0; l < L; ++l) atomicAdd(w + l, (unsigned long long)k[l]);
+            for (int l = 0; l < L; ++l)
+                atomicAdd(reinterpret_cast<unsigned long long*>(w + l * lstride), (unsigned long long)k[l]);
         }
         if (epoch_left > 0 && --epoch_left == 0) {
             int sp;
@@ -482,7 +496,7 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_lds(const KT* __restrict__ ke
 #pragma unroll
         for (int l = 0; l < L; ++l) {
             long long s = 0;
-            for (int r = 0; r < R; ++r) s += bins[((size_t)g * R + r) * L + l];
+            for (int r = 0; r < R; ++r) s += bins[((size_t)l * (G + 1) + g) * R + r];
             pK[((size_t)blockIdx.x * L + l) * G + g] = s;
         }
     }
@@ -752,10 +766,10 @@ __global__ void __launch_bounds__(PART_BLOCK)
     report(status, err);
 }
 
-// Folds a workgroup's aligned LDS bins of group g (top `top`) and, if
-// given, the caller's state of that group into a canonical state.
+// Folds a workgroup's aligned LDS level sums of group g (K[l * ks], top
+// `top`) and the caller's state of that group into a canonical state.
 template <class AT, int L>
-__device__ __forceinline__ void fold_into_state(const long long* K, int top, AT* __restrict__ S,
+__device__ __forceinline__ void fold_into_state(const long long* K, int ks, int top, AT* __restrict__ S,
                                                 long long* __restrict__ C, int64_t G, int64_t g) {
     typedef Fmt<AT> F;
     constexpr int c = F::CARRY;
@@ -769,7 +783,7 @@ __device__ __forceinline__ void fold_into_state(const long long* K, int top, AT*
         lo[l] = (ls >= 0) ? state_lo(S[(size_t)ls * G + g]) : 0;
         long long x = 0;
 #pragma unroll
-        for (int q = 0; q < L; ++q) x = (q == lk) ? K[q] : x;
+        for (int q = 0; q < L; ++q) x = (q == lk) ? K[q * ks] : x;
         hi[l] += x >> c;
         lo[l] += x & ((1ll << c) - 1);
     }
@@ -812,12 +826,12 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_part(const uint16_t* __restri
     const int2* TOP = reinterpret_cast<const int2*>(bins + (size_t)(Gp + 1) * L);
     if (it.nchunks == 1) {
         for (int g = threadIdx.x; g < Gp; g += AGG_BLOCK)
-            fold_into_state<AT, L>(bins + (size_t)g * L, TOP[g].x, S, C, G, g0 + g);
+            fold_into_state<AT, L>(bins + g, Gp + 1, TOP[g].x, S, C, G, g0 + g);
     } else {
         for (int g = threadIdx.x; g < Gp; g += AGG_BLOCK) {
             ptop[(size_t)blockIdx.x * GP + g] = TOP[g].x;
 #pragma unroll
-            for (int l = 0; l < L; ++l) pK[((size_t)blockIdx.x * L + l) * GP + g] = bins[(size_t)g * L + l];
+            for (int l = 0; l < L; ++l) pK[((size_t)blockIdx.x * L + l) * GP + g] = bins[(size_t)l * (Gp + 1) + g];
         }
     }
     report(status, err);
