@@ -300,6 +300,7 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
     int sync = 0;      // synchronisations so far (selects the flag slot)
     int epoch_left = 0;  // tiles left in the current epoch (0: per-tile mode)
     int quiet = 0;     // consecutive per-tile synchronisations without a raise
+    bool ahead = false;  // this tile's tops were raised at the previous synchronisation
 
     // Synchronisation point: all deposits before it are done.  If a top was
     // raised since the last one, realign every group with P > TOP (its levels
@@ -373,7 +374,10 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
 
     for (int64_t base = c0; base < c1; base += AGG_TILE) {
         const int64_t nb = base + (int64_t)PREFETCH * AGG_TILE;
-        if (nb < c1) inr[PREFETCH] = load_tile<KT, VT, VEC, AGG_BLOCK>(keys, vals, nb, c1, kb[PREFETCH], vb[PREFETCH], off);
+        if (nb < c1)
+            inr[PREFETCH] = load_tile<KT, VT, VEC, AGG_BLOCK>(keys, vals, nb, c1, kb[PREFETCH], vb[PREFETCH], off);
+        else
+            inr[PREFETCH] = 0;
         const KT* kc = kb[0];
         const VT* vc = vb[0];
         const uint32_t inr_c = inr[0];
@@ -407,13 +411,32 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
         bool raise = false;
 #pragma unroll
         for (int i = 0; i < ROWS_PER_THREAD; ++i) raise = raise || (ji[i] > ai[i]);
-        if (epoch_left == 0) {
+        if (!EPOCH && ahead) {
+            // its rows' tops were raised and realigned with the previous tile
+            ahead = false;
+        } else if (epoch_left == 0) {
             // per-tile mode: raise the tops, synchronise, then deposit
             if (raise) {
                 sh.flag[sync % 3] = 1;
 #pragma unroll
                 for (int i = 0; i < ROWS_PER_THREAD; ++i)
                     if (ji[i] > ai[i]) atomicMax(&P[gi[i]], ji[i]);
+            }
+            if (!EPOCH) {
+                // look ahead: raise the tops of the prefetched tile's rows in
+                // the same synchronisation, so that tile needs none
+                int gn[ROWS_PER_THREAD], jn[ROWS_PER_THREAD];
+                bool cn = true;
+                classify_rows<false, KT, VT, AT>(kb[PREFETCH], vb[PREFETCH], inr[PREFETCH], G, gn, jn, cn);
+                bool rn = false;
+#pragma unroll
+                for (int i = 0; i < ROWS_PER_THREAD; ++i)
+                    if (jn[i] > TOP[gn[i]].x) {
+                        atomicMax(&P[gn[i]], jn[i]);
+                        rn = true;
+                    }
+                if (rn) sh.flag[sync % 3] = 1;
+                ahead = true;
             }
             int sp;
             const bool moved = synchronise(sp);
@@ -588,6 +611,10 @@ __global__ void __launch_bounds__(PART_WG) k_part_offsets(const int* __restrict_
 // Every partition starts at a multiple of PART_ALIGN rows; the padding slots
 // after its rows get local key 0 and value +0.0, which contribute nothing,
 // so work items span whole aligned ranges and can use vector loads.
+// The work table lists the items of split partitions (full chunks, the
+// heaviest work) first and single-item partitions after them: workgroups
+// are dispatched in table order, so the longest items start first and the
+// end of the pass is not held up by a late large item.
 constexpr int PART_ALIGN = 8;
 
 template <class VT>
@@ -596,30 +623,38 @@ __global__ void __launch_bounds__(PART_BLOCK) k_part_plan(const long long* __res
                                                           WorkItem* __restrict__ items, int* __restrict__ nitems,
                                                           uint16_t* __restrict__ lkey, VT* __restrict__ lval) {
     __shared__ long long sb[PART_BLOCK];
-    __shared__ int sw[PART_BLOCK];
+    __shared__ int sw[PART_BLOCK], ss[PART_BLOCK];
     const int t = threadIdx.x;
     const int per = (F + PART_BLOCK - 1) / PART_BLOCK;  // partitions per thread
     const int p0 = min(F, t * per), p1 = min(F, p0 + per);
     long long rs = 0;
-    int ws = 0;
+    int wsplit = 0, wsingle = 0;  // items of split partitions, of single-item ones
     for (int p = p0; p < p1; ++p) {
         const long long sz = (size[p] + PART_ALIGN - 1) / PART_ALIGN * PART_ALIGN;
+        const int nc = (int)((sz + chunk - 1) / chunk);
         rs += sz;
-        ws += (int)((sz + chunk - 1) / chunk);
+        if (nc > 1)
+            wsplit += nc;
+        else
+            wsingle += nc;
     }
     sb[t] = rs;
-    sw[t] = ws;
+    sw[t] = wsplit;
+    ss[t] = wsingle;
     __syncthreads();
     for (int o = 1; o < PART_BLOCK; o <<= 1) {
         const long long x = (t >= o) ? sb[t - o] : 0;
         const int y = (t >= o) ? sw[t - o] : 0;
+        const int z = (t >= o) ? ss[t - o] : 0;
         __syncthreads();
         sb[t] += x;
         sw[t] += y;
+        ss[t] += z;
         __syncthreads();
     }
+    const int nsplit = sw[PART_BLOCK - 1];  // split items come first
     long long b = sb[t] - rs;
-    int wi = sw[t] - ws;
+    int wa = sw[t] - wsplit, wb = nsplit + ss[t] - wsingle;
     for (int p = p0; p < p1; ++p) {
         const long long sz = (size[p] + PART_ALIGN - 1) / PART_ALIGN * PART_ALIGN;
         for (long long q = b + size[p]; q < b + sz; ++q) {
@@ -627,6 +662,7 @@ __global__ void __launch_bounds__(PART_BLOCK) k_part_plan(const long long* __res
             lval[q] = (VT)0;
         }
         const int nc = (int)((sz + chunk - 1) / chunk);
+        int& wi = (nc > 1) ? wa : wb;
         base[p] = b;
         wfirst[p] = wi;
         for (int c = 0; c < nc; ++c) {
@@ -642,7 +678,7 @@ __global__ void __launch_bounds__(PART_BLOCK) k_part_plan(const long long* __res
         b += sz;
         wi += nc;
     }
-    if (t == PART_BLOCK - 1) *nitems = sw[t];
+    if (t == PART_BLOCK - 1) *nitems = nsplit + ss[t];
 }
 
 // Exclusive scan of cnt[0..F) into off[0..F) by one 1024-thread block
