@@ -27,6 +27,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_agg_lds_lowcard_200M_g1024_L3_pmc.md")
+# the sources that define the low-cardinality aggregation kernel, hashed in this order
+KERNEL_SOURCES = ("repro.hip", "repro_agg.hpp", "repro_device.hpp")
 
 
 def measured_traffic():
@@ -41,8 +43,7 @@ def measured_traffic():
         return None
     vals = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("kernel_source_sha256", "traffic_")))
     csrc = os.path.join(ROOT, "paper_1802_09883_amd", "csrc")
-    h = hashlib.sha256(open(os.path.join(csrc, "repro.hip"), "rb").read() +
-                       open(os.path.join(csrc, "repro_device.hpp"), "rb").read()).hexdigest()
+    h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in KERNEL_SOURCES)).hexdigest()
     if vals.get("kernel_source_sha256") != h or "traffic_bytes_per_launch" not in vals:
         return None
     return int(vals["traffic_bytes_per_launch"])

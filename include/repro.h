@@ -12,8 +12,10 @@
  * finalisation equation of Sec. III-C.
  *
  * Conventions for every entry point:
- *   - All buffers are DEVICE pointers owned by the caller.  The library
- *     allocates nothing; scratch memory is the caller's `workspace`.
+ *   - All buffers are DEVICE pointers owned by the caller (except the job
+ *     and plan records of the batch calls, which live in host memory).  The
+ *     library allocates no device memory; scratch memory is the caller's
+ *     `workspace`.
  *   - Work is enqueued asynchronously on `stream` (0 = the null stream);
  *     results are visible after the stream is synchronised.
  *   - Host return value: REPRO_OK, or REPRO_EINVAL for invalid arguments
@@ -130,6 +132,89 @@ int repro_finalize(const void* states, int64_t num_groups, repro_scalar_t T, int
  */
 int repro_plain_groupby_sum(const void* keys, repro_key_t kt, const void* values, repro_scalar_t vt, int64_t n,
                             int64_t num_groups, double* out, uint32_t* status, hipStream_t stream);
+
+/*
+ * ------------------------------------------------------------ batches
+ *
+ * Many independent GroupBy-SUMs (jobs) in one persistent kernel launch.
+ * Each job is what repro_groupby_sum computes for its own rows, groups and
+ * level count (Sec. II-A; operator+=(ScalarT) and, across the pieces of a
+ * job, operator+=(repro) of Sec. IV); its result bits are the same as
+ * those of repro_groupby_sum on the same rows, whatever the batch, the
+ * configuration or the schedule.  All jobs of a batch share kt, vt and T.
+ *
+ * Work is cut into items (job, row chunk, group slice): a job whose groups
+ * do not fit one workgroup's LDS is cut into group slices, every item of a
+ * slice reads the chunk and keeps only its slice's groups (the other items
+ * of the chunk read it at about the same time, mostly from cache).  Items
+ * are taken from a queue in order of decreasing size; the last item of a
+ * (job, slice) to finish folds that slice's partial sums into the states
+ * (and finalises them into `out`, when given).
+ *
+ * Use: repro_batch_workspace_bytes -> repro_batch_prepare (host planning,
+ * uploads the plan into the workspace and waits for that copy) ->
+ * repro_batch_launch (kernels only: may be captured into a HIP graph and
+ * replayed; every launch recomputes the whole batch).  The plan stays valid
+ * while the workspace and the jobs' buffers do.
+ */
+typedef struct {
+    const void* keys;    /* device, kt, n entries                                  */
+    const void* values;  /* device, vt, n entries                                  */
+    int64_t n;           /* rows, >= 0                                             */
+    int64_t num_groups;  /* 1 .. 2^31-1                                            */
+    int L;               /* levels, 1..4                                           */
+    int accumulate;      /* 1: add into `states`; 0: overwrite them with this batch */
+    void* states;        /* device state buffer of the job (layout above)          */
+    void* out;           /* device T[num_groups] finalised sums, or NULL           */
+} repro_batch_job;
+
+/* Tuning knobs.  None of them changes a result bit.  Zero fields take the
+ * defaults (chunk_rows 131072, max_slice_groups as large as LDS allows,
+ * order 0). */
+typedef struct {
+    int64_t chunk_rows;   /* rows per item (rounded up to a multiple of 8192)  */
+    int max_slice_groups; /* cap on the groups of one slice (bins per LDS)     */
+    int order;            /* 0: largest items first, 1: job order              */
+} repro_batch_config;
+
+/* Plan handle filled by repro_batch_prepare (host memory, plain data). */
+typedef struct {
+    void* workspace;
+    int64_t items;
+    int grid, lds_bytes;
+    int kt, vt, T;
+    int reserved[4];
+} repro_batch_plan;
+
+/* Workspace bytes for this batch and configuration (cfg may be NULL);
+ * 0 for invalid arguments. */
+size_t repro_batch_workspace_bytes(const repro_batch_job* jobs, int njobs, repro_key_t kt, repro_scalar_t vt,
+                                   repro_scalar_t T, const repro_batch_config* cfg);
+
+/* Validates the jobs (host array) and the configuration, plans the items
+ * and copies the plan into `workspace` on `stream` (then waits for the
+ * stream).  REPRO_EINVAL for invalid jobs (a NULL pointer a job needs, L
+ * outside 1..4, num_groups out of range, vt = F64 with T = F32, more than
+ * 2^31 rows in a job) or a workspace too small or not 256-byte aligned. */
+int repro_batch_prepare(const repro_batch_job* jobs, int njobs, repro_key_t kt, repro_scalar_t vt, repro_scalar_t T,
+                        const repro_batch_config* cfg, void* workspace, size_t workspace_bytes,
+                        repro_batch_plan* plan, hipStream_t stream);
+
+/* Runs a prepared batch on `stream`: a reset kernel, then the persistent
+ * kernel.  status as for repro_groupby_sum (may be NULL).  Jobs that
+ * accumulate must see their states' previous contents, so two launches of
+ * the same plan add the batch twice; jobs that overwrite give the same
+ * states every launch. */
+int repro_batch_launch(const repro_batch_plan* plan, uint32_t* status, hipStream_t stream);
+
+/* Autotuner: times the candidate configurations (chunk rows, slice cap,
+ * order) on this batch and writes the fastest to *best (and its time in ms
+ * to *best_ms, if not NULL).  It runs the batch many times: the jobs'
+ * states and outputs hold unspecified values afterwards.  Candidates whose
+ * workspace exceeds workspace_bytes are skipped.  Blocks until done. */
+int repro_batch_tune(const repro_batch_job* jobs, int njobs, repro_key_t kt, repro_scalar_t vt, repro_scalar_t T,
+                     void* workspace, size_t workspace_bytes, repro_batch_config* best, float* best_ms,
+                     hipStream_t stream);
 
 /*
  * Profiling aid.  repro_profile_arm(k) makes the next k repro_groupby_sum

@@ -25,479 +25,11 @@
 
 #include "repro.h"
 #include "repro_device.hpp"
+#include "repro_agg.hpp"
 
 using namespace repro;
 
 namespace {
-
-constexpr int AGG_BLOCK = 1024;  // 16 waves: one workgroup per CU
-constexpr int ROWS_PER_THREAD = 8;
-constexpr int PREFETCH = 1;  // tiles loaded ahead of the one being processed
-constexpr int AGG_TILE = AGG_BLOCK * ROWS_PER_THREAD;
-constexpr int MAX_AGG_WG = 256;
-constexpr int64_t MIN_ROWS_PER_WG = 4 * (int64_t)AGG_TILE;
-// A bin word takes at most (rows of one workgroup) units of magnitude
-// <= 2^(W-1) <= 2^39; 2^23 rows keep it below 2^62.
-constexpr int64_t MAX_ROWS_PER_WG = (int64_t)1 << 23;
-constexpr size_t LDS_BIN_BUDGET = 150 * 1024;  // of gfx950's 160 KiB per workgroup
-constexpr size_t REPLICA_BUDGET = 32 * 1024;
-
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-// ----------------------------------------------------------- row loading
-
-template <class T, int N>
-struct VecT {
-    typedef T type __attribute__((ext_vector_type(N)));
-};
-
-template <class T, int N>
-__device__ __forceinline__ void vload(const T* __restrict__ p, T* out) {
-    if constexpr (N == 1) {
-        out[0] = *p;
-    } else {
-        typedef typename VecT<T, N>::type V;
-        const V x = *reinterpret_cast<const V*>(p);
-#pragma unroll
-        for (int i = 0; i < N; ++i) out[i] = x[i];
-    }
-}
-
-// Loads the ROWS_PER_THREAD rows of this thread in the tile starting at
-// `base`: unit u covers rows base + off[u] + [0, VEC) with off[u] =
-// (u*BLOCK + tid)*VEC, so each vector load instruction of a wave reads one
-// contiguous span (the tile base is uniform, the offsets are 32-bit).  Rows
-// at or beyond `end` are flagged out of range.
-template <class KT, class VT, int VEC, int BLOCK>
-__device__ __forceinline__ uint32_t load_tile(const KT* __restrict__ keys, const VT* __restrict__ vals,
-                                              int64_t base, int64_t end, KT* k, VT* v, const uint32_t* off) {
-    constexpr int U = ROWS_PER_THREAD / VEC;
-    const KT* kb = keys + base;
-    const VT* vb = vals + base;
-    uint32_t inr = 0;
-    if (base + (int64_t)BLOCK * ROWS_PER_THREAD <= end) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            vload<KT, VEC>(kb + off[u], k + u * VEC);
-            vload<VT, VEC>(vb + off[u], v + u * VEC);
-        }
-        inr = (1u << ROWS_PER_THREAD) - 1;
-    } else {
-        const uint32_t lim = (uint32_t)(end - base);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                const uint32_t row = off[u] + e;
-                if (row < lim) {
-                    k[u * VEC + e] = kb[row];
-                    v[u * VEC + e] = vb[row];
-                    inr |= 1u << (u * VEC + e);
-                } else {
-                    k[u * VEC + e] = 0;
-                    v[u * VEC + e] = (VT)0;
-                }
-            }
-        }
-    }
-    return inr;
-}
-
-__device__ __forceinline__ uint32_t wave_or(uint32_t x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, 64);
-    return x;
-}
-
-__device__ __forceinline__ void report(uint32_t* status, uint32_t err) {
-    err = wave_or(err);
-    if (status && err && (threadIdx.x & 63) == 0) atomicOr(status, err);
-}
-
-// ------------------------------------------------------ the hot kernel
-//
-// LDS layout (G real groups plus one trash slot G that absorbs skipped
-// rows, so the deposit loop has no per-row branch):
-//   bins[L][G+1][R]  int64 level sums; lane r deposits into replica r % R
-//                    (R > 1 only when groups are few, to spread contention).
-//                    Level-major, so that the words one level-add of a wave
-//                    touches (random groups) spread over all LDS banks for
-//                    every L; a group-major layout with a 16- or 32-byte
-//                    group stride would use only part of the banks.
-//   TOP[G+1]         {top index, high word of the level-0 extractor}
-//   P[G+1]           pending top, raised with ds_max while a tile is read
-// A workgroup-uniform fast path applies while every group sits at the same
-// top Ju ("uni"): then no per-row LDS read of the top is needed.
-struct AggShared {
-    int newmax;     // largest top after a realignment
-    int cnt;        // groups at newmax
-    int flag[3];    // "some top was raised" per synchronisation (3 rotating slots)
-    int spills[3];  // rows deposited into the spill array, per synchronisation
-};
-
-__device__ __forceinline__ uint32_t extractor_hi_of(double*, int top) {
-    return extractor_hi((double*)0, Fmt<double>::B + top * Fmt<double>::W);
-}
-__device__ __forceinline__ uint32_t extractor_hi_of(float*, int top) {
-    return extractor_hi((float*)0, Fmt<float>::B + top * Fmt<float>::W);
-}
-
-// Units of one value given the extractor bits of its level 0 (see
-// extract_units): the extractor of level l is 2^(l*W) smaller.
-template <int L>
-__device__ __forceinline__ void extract_from_hi(double b, uint32_t h0, long long* k) {
-    double r = b;
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        const uint32_t mh = h0 - (uint32_t)(l * Fmt<double>::W) * (1u << 20);
-        const double M = __hiloint2double((int)mh, 0);
-        const double s = r + M;
-        if (l + 1 < L) {
-            const double t = s - M;
-            r = r - t;
-        }
-        const uint64_t sb = (uint64_t)__double_as_longlong(s);
-        k[l] = (long long)(((uint64_t)((uint32_t)(sb >> 32) - mh) << 32) | (sb & 0xffffffffull));
-    }
-}
-template <int L>
-__device__ __forceinline__ void extract_from_hi(float b, uint32_t b0, long long* k) {
-    float r = b;
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        const uint32_t mb = b0 - (uint32_t)(l * Fmt<float>::W) * (1u << 23);
-        const float M = __uint_as_float(mb);
-        const float s = r + M;
-        k[l] = (long long)(int32_t)(__float_as_uint(s) - mb);
-        if (l + 1 < L) {
-            const float t = s - M;
-            r = r - t;
-        }
-    }
-}
-
-// Smallest top index able to take b (jreq_of_exp) from the raw v_frexp
-// exponent f = e + 1 of a finite nonzero value, branch-free: with
-// x = f + m - W + 2 - B + W - 2 in [1, 2^11], floor(x / W) equals
-// (x * ceil(2^16 / W)) >> 16 for W = 40 and W = 18 on that whole range;
-// one 24-bit multiply-add.
-template <class AT>
-__device__ __forceinline__ int jreq_raw(int f) {
-    typedef Fmt<AT> F;
-    constexpr int mul = (65536 + F::W - 1) / F::W;
-    constexpr int add = (F::m - F::W + 2 - F::B + F::W - 2) * mul;
-    return (int)((uint32_t)__mul24(f, mul) + (uint32_t)add) >> 16;
-}
-__device__ __forceinline__ int frexp_raw(double v) { return __builtin_amdgcn_frexp_exp(v); }
-__device__ __forceinline__ int frexp_raw(float v) { return __builtin_amdgcn_frexp_expf(v); }
-
-// Per-row classification of a tile.  A row is deposited when its key is a
-// group id, its value finite, nonzero and inside the domain of AT; other
-// rows go to the trash slot G with required top 0.  `clean` stays true
-// while no row of this lane is an error (zero values are not errors).
-template <bool FULL, class KT, class VT, class AT>
-__device__ __forceinline__ void classify_rows(const KT* kc, const VT* vc, uint32_t inr, int G, int* gi, int* ji,
-                                              bool& clean) {
-#pragma unroll
-    for (int i = 0; i < ROWS_PER_THREAD; ++i) {
-        const VT v = vc[i];
-        const bool in = FULL || ((inr >> i) & 1u);
-        const bool kok = (uint64_t)(int64_t)kc[i] < (uint64_t)G;
-        const bool fin = finite_val(v);
-        const bool nz = v != (VT)0;
-        const int j = jreq_raw<AT>(frexp_raw(v));
-        const bool dom = j <= Fmt<AT>::JMAX;
-        const bool use = in && kok && fin && nz && dom;
-        clean = clean && (!in || (kok && fin && (dom || !nz)));
-        gi[i] = use ? (int)kc[i] : G;
-        ji[i] = use ? j : 0;
-    }
-}
-
-// Status bits of the error rows among this lane's rows (slow path).
-template <class KT, class VT, class AT>
-__device__ __forceinline__ uint32_t error_bits(const KT* kc, const VT* vc, uint32_t inr, int G) {
-    uint32_t e = 0;
-    for (int i = 0; i < ROWS_PER_THREAD; ++i) {
-        if (!((inr >> i) & 1u)) continue;
-        const VT v = vc[i];
-        if ((uint64_t)(int64_t)kc[i] >= (uint64_t)G) e |= ERR_KEY;
-        if (!finite_val(v))
-            e |= ERR_NONFINITE;
-        else if (v != (VT)0 && jreq_raw<AT>(frexp_raw(v)) > Fmt<AT>::JMAX)
-            e |= ERR_RANGE;
-    }
-    return e;
-}
-
-// Exact add of a unit into a spill word pair {w, H} holding H * 2^64 + w
-// (w unsigned): the atomic add returns the old w, from which the carry out
-// of this add (-1, 0 or +1) follows; it is added to H.
-__device__ __forceinline__ void spill_add(unsigned long long* w, long long k) {
-    const unsigned long long old = atomicAdd(w, (unsigned long long)k);
-    const unsigned long long nw = old + (unsigned long long)k;
-    const long long c = (k >= 0) ? (nw < old ? 1 : 0) : (nw > old ? -1 : 0);
-    if (c) atomicAdd(w + 1, (unsigned long long)c);
-}
-
-// A row whose group's bins are aligned below its required top: its units
-// are extracted at its own top jr (own-window deposit) and added into the
-// spill array at their absolute lattice indices jr - l.  Extraction at any
-// top between jr and the group's final top gives the same units at every
-// lattice index the final state keeps, so nothing has to move later.
-template <class AT, int L>
-__device__ __forceinline__ void spill_row(unsigned long long* __restrict__ spill, int g, AT v, int jr) {
-    constexpr int NJ = Fmt<AT>::JMAX + 1;
-    long long k[L];
-    extract_from_hi<L>(v, extractor_hi_of((AT*)0, jr), k);
-#pragma unroll
-    for (int l = 0; l < L; ++l) spill_add(spill + ((size_t)g * NJ + (jr - l)) * 2, k[l]);
-}
-
-constexpr int EPOCH_TILES = 16;  // tiles between synchronisations in epoch mode
-constexpr int QUIET_TILES = 1;   // quiet per-tile synchronisations before epoch mode
-
-// The aggregation of rows [c0, c1) into LDS by one workgroup (the hot loop
-// of both aggregation kernels).  On return the bins are aligned to every
-// group's top (TOP), and the lane's status bits are returned.  EPOCH
-// enables epoch mode, which needs the spill array, and the tracking of a
-// top shared by all groups (few groups, whose tops settle early); without
-// it every tile synchronises and rows read their group's top from LDS.
-template <class KT, class VT, class AT, int L, int VEC, bool EPOCH>
-__device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys, const VT* __restrict__ vals,
-                                                    int64_t c0, int64_t c1, int G, int R, unsigned char* smem,
-                                                    AggShared& sh, unsigned long long* __restrict__ spill) {
-    typedef Fmt<AT> F;
-    constexpr int U = ROWS_PER_THREAD / VEC;
-    long long* bins = reinterpret_cast<long long*>(smem);
-    int2* TOP = reinterpret_cast<int2*>(bins + (size_t)(G + 1) * R * L);
-    int* P = reinterpret_cast<int*>(TOP + (G + 1));
-
-    const int tid = threadIdx.x;
-    const int rep = (tid & 63) & (R - 1);
-    const uint32_t gstride = (uint32_t)(R * 8);             // bytes per group in a level
-    const uint32_t lstride = (uint32_t)((G + 1) * R * 8);   // bytes per level
-    const uint32_t lane_off = (uint32_t)(rep * 8);
-    for (int i = tid; i < (G + 1) * R * L; i += AGG_BLOCK) bins[i] = 0;
-    const uint32_t h_init = extractor_hi_of((AT*)0, L - 1);
-    for (int i = tid; i < G; i += AGG_BLOCK) {
-        TOP[i] = make_int2(L - 1, (int)h_init);
-        P[i] = L - 1;
-    }
-    if (tid == 0) {
-        TOP[G] = make_int2(F::JMAX, (int)extractor_hi_of((AT*)0, F::JMAX));  // trash slot: never raised
-        P[G] = F::JMAX;
-        sh.newmax = L - 1;
-        sh.cnt = G;
-        for (int q = 0; q < 3; ++q) sh.flag[q] = sh.spills[q] = 0;
-    }
-    __syncthreads();
-
-    // workgroup-uniform state
-    bool uni = true;   // all groups aligned to top Ju
-    int Ju = L - 1;
-    uint32_t hu = h_init;
-    int sync = 0;      // synchronisations so far (selects the flag slot)
-    int epoch_left = 0;  // tiles left in the current epoch (0: per-tile mode)
-    int quiet = 0;     // consecutive per-tile synchronisations without a raise
-    bool ahead = false;  // this tile's tops were raised at the previous synchronisation
-
-    // Synchronisation point: all deposits before it are done.  If a top was
-    // raised since the last one, realign every group with P > TOP (its levels
-    // move down by the rise, the lowest fall off: the level shift of Alg. 2)
-    // and recompute whether all groups share one top.  Returns whether rows
-    // went to the spill array since the last synchronisation.
-    auto synchronise = [&](int& spilled) {
-        __syncthreads();
-        const int f = sh.flag[sync % 3];
-        spilled = sh.spills[sync % 3];
-        if (tid == 0) {  // slot (sync+2)%3 was read at the previous synchronisation
-            sh.flag[(sync + 2) % 3] = 0;   // and is next written after the following one
-            sh.spills[(sync + 2) % 3] = 0;
-        }
-        ++sync;
-        if (!f) return false;
-        int m = -1;
-        for (int g = tid; g < G; g += AGG_BLOCK) {
-            const int p = P[g];
-            int top = TOP[g].x;
-            if (p > top) {
-                const int d = p - top;
-                const size_t ls = (size_t)(G + 1) * R;  // words per level
-                for (int r = 0; r < R; ++r) {
-                    long long* w = bins + (size_t)g * R + r;
-#pragma unroll
-                    for (int l = L - 1; l >= 0; --l) w[l * ls] = (l - d >= 0) ? w[(l - d) * ls] : 0;
-                }
-                TOP[g] = make_int2(p, (int)extractor_hi_of((AT*)0, p));
-                top = p;
-            }
-            m = max(m, top);
-        }
-        if (!EPOCH) {
-            // many groups whose tops rise at different times: no shared top
-            __syncthreads();
-            uni = false;
-            return true;
-        }
-        if (tid == 0) sh.cnt = 0;
-        atomicMax(&sh.newmax, m);  // newmax only grows: tops never fall
-        __syncthreads();
-        const int nm = sh.newmax;
-        int c = 0;
-        for (int g = tid; g < G; g += AGG_BLOCK) c += (TOP[g].x == nm);
-        if (c) atomicAdd(&sh.cnt, c);
-        __syncthreads();
-        uni = (sh.cnt == G);
-        Ju = nm;
-        hu = extractor_hi_of((AT*)0, Ju);
-        return true;
-    };
-
-    uint32_t err = 0;
-
-    uint32_t off[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) off[u] = (uint32_t)((u * AGG_BLOCK + tid) * VEC);
-
-    // software pipeline: tiles base+AGG_TILE .. base+PREFETCH*AGG_TILE are in
-    // flight (in registers) while tile `base` is processed
-    KT kb[PREFETCH + 1][ROWS_PER_THREAD];
-    VT vb[PREFETCH + 1][ROWS_PER_THREAD];
-    uint32_t inr[PREFETCH + 1];
-#pragma unroll
-    for (int q = 0; q <= PREFETCH; ++q) inr[q] = 0;
-#pragma unroll
-    for (int q = 0; q < PREFETCH; ++q)
-        if (c0 + (int64_t)q * AGG_TILE < c1)
-            inr[q] = load_tile<KT, VT, VEC, AGG_BLOCK>(keys, vals, c0 + (int64_t)q * AGG_TILE, c1, kb[q], vb[q], off);
-
-    for (int64_t base = c0; base < c1; base += AGG_TILE) {
-        const int64_t nb = base + (int64_t)PREFETCH * AGG_TILE;
-        if (nb < c1)
-            inr[PREFETCH] = load_tile<KT, VT, VEC, AGG_BLOCK>(keys, vals, nb, c1, kb[PREFETCH], vb[PREFETCH], off);
-        else
-            inr[PREFETCH] = 0;
-        const KT* kc = kb[0];
-        const VT* vc = vb[0];
-        const uint32_t inr_c = inr[0];
-
-        // classify: group (trash slot G for skipped rows) and required top
-        int gi[ROWS_PER_THREAD], ji[ROWS_PER_THREAD];
-        bool clean = true;  // no row of this lane is an error row
-        if (base + AGG_TILE <= c1)
-            classify_rows<true, KT, VT, AT>(kc, vc, inr_c, G, gi, ji, clean);
-        else
-            classify_rows<false, KT, VT, AT>(kc, vc, inr_c, G, gi, ji, clean);
-        if (!clean) err |= error_bits<KT, VT, AT>(kc, vc, base + AGG_TILE <= c1 ? 0xffu : inr_c, G);
-
-        // tops of the rows' groups
-        int ai[ROWS_PER_THREAD];
-        uint32_t hi_[ROWS_PER_THREAD];
-        if (uni) {
-#pragma unroll
-            for (int i = 0; i < ROWS_PER_THREAD; ++i) {
-                ai[i] = Ju;
-                hi_[i] = hu;
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < ROWS_PER_THREAD; ++i) {
-                const int2 tp = TOP[gi[i]];
-                ai[i] = tp.x;
-                hi_[i] = (uint32_t)tp.y;
-            }
-        }
-        bool raise = false;
-#pragma unroll
-        for (int i = 0; i < ROWS_PER_THREAD; ++i) raise = raise || (ji[i] > ai[i]);
-        if (!EPOCH && ahead) {
-            // its rows' tops were raised and realigned with the previous tile
-            ahead = false;
-        } else if (epoch_left == 0) {
-            // per-tile mode: raise the tops, synchronise, then deposit
-            if (raise) {
-                sh.flag[sync % 3] = 1;
-#pragma unroll
-                for (int i = 0; i < ROWS_PER_THREAD; ++i)
-                    if (ji[i] > ai[i]) atomicMax(&P[gi[i]], ji[i]);
-            }
-            if (!EPOCH) {
-                // look ahead: raise the tops of the prefetched tile's rows in
-                // the same synchronisation, so that tile needs none
-                int gn[ROWS_PER_THREAD], jn[ROWS_PER_THREAD];
-                bool cn = true;
-                classify_rows<false, KT, VT, AT>(kb[PREFETCH], vb[PREFETCH], inr[PREFETCH], G, gn, jn, cn);
-                bool rn = false;
-#pragma unroll
-                for (int i = 0; i < ROWS_PER_THREAD; ++i)
-                    if (jn[i] > TOP[gn[i]].x) {
-                        atomicMax(&P[gn[i]], jn[i]);
-                        rn = true;
-                    }
-                if (rn) sh.flag[sync % 3] = 1;
-                ahead = true;
-            }
-            int sp;
-            const bool moved = synchronise(sp);
-            quiet = moved ? 0 : quiet + 1;
-            if (EPOCH && quiet >= QUIET_TILES) epoch_left = EPOCH_TILES;
-            if (moved) {
-                if (uni) {
-#pragma unroll
-                    for (int i = 0; i < ROWS_PER_THREAD; ++i) hi_[i] = hu;
-                } else {
-#pragma unroll
-                    for (int i = 0; i < ROWS_PER_THREAD; ++i) hi_[i] = (uint32_t)TOP[gi[i]].y;
-                }
-            }
-        } else if (raise) {
-            // epoch mode: rows above their group's top go to the spill array
-            int ns = 0;
-#pragma unroll
-            for (int i = 0; i < ROWS_PER_THREAD; ++i) {
-                if (ji[i] > ai[i]) {
-                    atomicMax(&P[gi[i]], ji[i]);
-                    spill_row<AT, L>(spill, gi[i], (AT)vc[i], ji[i]);
-                    gi[i] = G;  // nothing more for the bins
-                    ++ns;
-                }
-            }
-            sh.flag[sync % 3] = 1;
-            atomicAdd(&sh.spills[sync % 3], ns);
-        }
-        // extract and deposit (skipped rows go to the trash slot)
-#pragma unroll
-        for (int i = 0; i < ROWS_PER_THREAD; ++i) {
-            long long k[L];
-            extract_from_hi<L>((AT)vc[i], hi_[i], k);
-            unsigned char* w = smem + __umul24((uint32_t)gi[i], gstride) + lane_off;
-#pragma unroll
-            for (int l = 0; l < L; ++l)
-                atomicAdd(reinterpret_cast<unsigned long long*>(w + l * lstride), (unsigned long long)k[l]);
-        }
-        if (epoch_left > 0 && --epoch_left == 0) {
-            int sp;
-            synchronise(sp);
-            // many spills: the tops are still moving, go back to per-tile mode
-            epoch_left = (sp > AGG_TILE / 16) ? 0 : EPOCH_TILES;
-            quiet = 0;
-        }
-#pragma unroll
-        for (int q = 0; q < PREFETCH; ++q) {
-#pragma unroll
-            for (int i = 0; i < ROWS_PER_THREAD; ++i) {
-                kb[q][i] = kb[q + 1][i];
-                vb[q][i] = vb[q + 1][i];
-            }
-            inr[q] = inr[q + 1];
-        }
-    }
-    // final synchronisation: tops include every spilled row, bins aligned
-    int sp;
-    synchronise(sp);
-    return err;
-}
 
 // Low/mid cardinality: each workgroup aggregates a contiguous chunk of rows
 // over all groups and writes its partial (top, K[L]) per group.
@@ -800,36 +332,6 @@ __global__ void __launch_bounds__(PART_BLOCK)
         for (int i = t; i < F; i += PART_BLOCK) cur[i] += cnt[i];
     }
     report(status, err);
-}
-
-// Folds a workgroup's aligned LDS level sums of group g (K[l * ks], top
-// `top`) and the caller's state of that group into a canonical state.
-template <class AT, int L>
-__device__ __forceinline__ void fold_into_state(const long long* K, int ks, int top, AT* __restrict__ S,
-                                                long long* __restrict__ C, int64_t G, int64_t g) {
-    typedef Fmt<AT> F;
-    constexpr int c = F::CARRY;
-    const int ts = state_top(S[g]);
-    const int J = max(top, ts);
-    long long hi[L], lo[L];
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        const int ls = l - (J - ts), lk = l - (J - top);
-        hi[l] = (ls >= 0) ? C[(size_t)ls * G + g] : 0;
-        lo[l] = (ls >= 0) ? state_lo(S[(size_t)ls * G + g]) : 0;
-        long long x = 0;
-#pragma unroll
-        for (int q = 0; q < L; ++q) x = (q == lk) ? K[q * ks] : x;
-        hi[l] += x >> c;
-        lo[l] += x & ((1ll << c) - 1);
-    }
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        long long cc, oo;
-        normalise<AT>(hi[l], lo[l], &cc, &oo);
-        S[(size_t)l * G + g] = make_S((AT*)0, F::B + (J - l) * F::W, oo);
-        C[(size_t)l * G + g] = cc;
-    }
 }
 
 // One work item (a chunk of one partition): the partition's groups are
@@ -1256,11 +758,6 @@ bool valid_common(int64_t G, repro_scalar_t T, int L) {
     return G >= 1 && G <= INT32_MAX && (T == REPRO_F32 || T == REPRO_F64) && L >= 1 && L <= 4;
 }
 
-int replicas_for(int64_t G, int L) {
-    int R = 1;
-    while (R < 64 && (size_t)2 * R * G * L * 8 <= REPLICA_BUDGET) R *= 2;
-    return R;
-}
 
 // High cardinality: partition, then aggregate every partition in LDS.
 bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
@@ -1302,11 +799,11 @@ bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
 
 bool make_plan(int64_t n, int64_t G, int L, int jmax, size_t vsize, Plan* p) {
     memset(p, 0, sizeof(*p));
-    const size_t lds1 = (size_t)(G + 1) * L * 8 + (size_t)(G + 1) * 12;
+    const size_t lds1 = agg_lds_bytes(G, L, 1);
     if (lds1 > LDS_BIN_BUDGET) return make_plan_part(n, G, L, vsize, p);
     p->path = 1;
     p->R = replicas_for(G, L);
-    p->lds = (size_t)(G + 1) * L * 8 * p->R + (size_t)(G + 1) * 12;
+    p->lds = agg_lds_bytes(G, L, p->R);
     int64_t nwg = (n + MIN_ROWS_PER_WG - 1) / MIN_ROWS_PER_WG;
     if (nwg > MAX_AGG_WG) nwg = MAX_AGG_WG;
     if (nwg < (n + MAX_ROWS_PER_WG - 1) / MAX_ROWS_PER_WG) nwg = (n + MAX_ROWS_PER_WG - 1) / MAX_ROWS_PER_WG;
