@@ -21,6 +21,25 @@ I32, I64 = 0, 1
 _lib = None
 
 
+class BatchJob(ctypes.Structure):
+    """repro_batch_job of include/repro.h."""
+    _fields_ = [("keys", ctypes.c_void_p), ("values", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("num_groups", ctypes.c_int64), ("L", ctypes.c_int), ("accumulate", ctypes.c_int),
+                ("states", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+class BatchConfig(ctypes.Structure):
+    """repro_batch_config of include/repro.h."""
+    _fields_ = [("chunk_rows", ctypes.c_int64), ("max_slice_groups", ctypes.c_int), ("order", ctypes.c_int)]
+
+
+class BatchPlan(ctypes.Structure):
+    """repro_batch_plan of include/repro.h."""
+    _fields_ = [("workspace", ctypes.c_void_p), ("items", ctypes.c_int64), ("grid", ctypes.c_int),
+                ("lds_bytes", ctypes.c_int), ("kt", ctypes.c_int), ("vt", ctypes.c_int), ("T", ctypes.c_int),
+                ("reserved", ctypes.c_int * 4)]
+
+
 def header_functions():
     """Names of the functions declared in include/repro.h."""
     with open(HEADER) as fh:
@@ -49,6 +68,15 @@ def load():
     lib.repro_profile_arm.restype = ctypes.c_int
     lib.repro_profile_read.argtypes = [vp, i32, vp]
     lib.repro_profile_read.restype = ctypes.c_int
+    bj, bc, bp = ctypes.POINTER(BatchJob), ctypes.POINTER(BatchConfig), ctypes.POINTER(BatchPlan)
+    lib.repro_batch_workspace_bytes.restype = sz
+    lib.repro_batch_workspace_bytes.argtypes = [bj, i32, i32, i32, i32, bc]
+    lib.repro_batch_prepare.restype = ctypes.c_int
+    lib.repro_batch_prepare.argtypes = [bj, i32, i32, i32, i32, bc, vp, sz, bp, vp]
+    lib.repro_batch_launch.restype = ctypes.c_int
+    lib.repro_batch_launch.argtypes = [bp, vp, vp]
+    lib.repro_batch_tune.restype = ctypes.c_int
+    lib.repro_batch_tune.argtypes = [bj, i32, i32, i32, i32, vp, sz, bc, ctypes.POINTER(ctypes.c_float), vp]
     lib.repro_version.restype = ctypes.c_char_p
     lib.repro_version.argtypes = []
     for name in ("repro_state_init", "repro_groupby_sum", "repro_merge", "repro_finalize",

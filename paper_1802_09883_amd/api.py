@@ -158,3 +158,99 @@ def state_reset(states: torch.Tensor, num_groups: int, L: int = 2, T=torch.float
     _lib.check(_lib.load().repro_state_init(_vp(states), num_groups, _T(T), L, _stream(states.device, stream)),
                "state_init")
     return states
+
+
+# ----------------------------------------------------------------- batches
+
+class Job:
+    """One GroupBy-SUM of a batch: its key and value columns (device tensors),
+    group count, levels and state buffer; ``out`` (optional) receives the
+    finalised sums; ``accumulate`` adds into the states instead of
+    overwriting them."""
+
+    def __init__(self, keys, values, num_groups, L, states, out=None, accumulate=False):
+        self.keys, self.values, self.num_groups, self.L = keys, values, int(num_groups), int(L)
+        self.states, self.out, self.accumulate = states, out, bool(accumulate)
+
+
+def _batch_jobs(jobs):
+    arr = (_lib.BatchJob * max(1, len(jobs)))()
+    for i, j in enumerate(jobs):
+        if j.keys.dtype != jobs[0].keys.dtype or j.values.dtype != jobs[0].values.dtype:
+            raise TypeError("all jobs of a batch share the key and value dtypes")
+        arr[i] = _lib.BatchJob(_vp(j.keys).value, _vp(j.values).value, j.keys.numel(), j.num_groups, j.L,
+                               int(j.accumulate), _vp(j.states).value, _vp(j.out).value if j.out is not None else None)
+    return arr
+
+
+def _batch_config(config):
+    if config is None:
+        return None
+    return ctypes.byref(_lib.BatchConfig(int(config.get("chunk_rows", 0)), int(config.get("max_slice_groups", 0)),
+                                         int(config.get("order", 0))))
+
+
+class BatchRun:
+    """A prepared batch: the plan, its workspace and references to the jobs'
+    tensors (kept alive while the plan may be launched)."""
+
+    def __init__(self, plan, workspace, jobs):
+        self.plan, self.workspace, self.jobs = plan, workspace, jobs
+
+
+def batch_prepare(jobs, T=torch.float64, config=None, stream=None) -> BatchRun:
+    """Plans the batch and uploads the plan into a fresh workspace."""
+    lib = _lib.load()
+    if not jobs:
+        raise ValueError("empty batch")
+    for j in jobs:
+        if j.keys.shape != j.values.shape or j.keys.dim() != 1 or not j.keys.is_contiguous() \
+                or not j.values.is_contiguous():
+            raise ValueError("job columns must be contiguous 1-D tensors of equal length")
+    dev = jobs[0].keys.device
+    arr = _batch_jobs(jobs)
+    kt, vt = _KEY[jobs[0].keys.dtype], _SCALAR[jobs[0].values.dtype]
+    cfg = _batch_config(config)
+    need = lib.repro_batch_workspace_bytes(arr, len(jobs), kt, vt, _T(T), cfg)
+    if need == 0:
+        raise ValueError("batch_prepare: invalid jobs or configuration")
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    with torch.cuda.stream(s):
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    plan = _lib.BatchPlan()
+    _lib.check(lib.repro_batch_prepare(arr, len(jobs), kt, vt, _T(T), cfg, _vp(ws), need, ctypes.byref(plan),
+                                       ctypes.c_void_p(s.cuda_stream)), "batch_prepare")
+    return BatchRun(plan, ws, list(jobs))
+
+
+def batch_launch(run: BatchRun, status=None, stream=None):
+    """Runs a prepared batch (kernels only; may be captured into a graph)."""
+    s = stream if stream is not None else torch.cuda.current_stream(run.workspace.device)
+    _lib.check(_lib.load().repro_batch_launch(ctypes.byref(run.plan), _vp(status), ctypes.c_void_p(s.cuda_stream)),
+               "batch_launch")
+
+
+def batch_groupby_sum(jobs, T=torch.float64, config=None, status=None, stream=None) -> BatchRun:
+    """Prepare and launch a batch; returns the prepared run for re-launches."""
+    run = batch_prepare(jobs, T, config, stream)
+    batch_launch(run, status, stream)
+    return run
+
+
+def batch_tune(jobs, T=torch.float64, stream=None):
+    """The autotuner: returns (best config dict, its milliseconds).  The jobs'
+    states and outputs hold unspecified values afterwards."""
+    lib = _lib.load()
+    dev = jobs[0].keys.device
+    arr = _batch_jobs(jobs)
+    kt, vt = _KEY[jobs[0].keys.dtype], _SCALAR[jobs[0].values.dtype]
+    need = max(lib.repro_batch_workspace_bytes(arr, len(jobs), kt, vt, _T(T),
+                                               _batch_config({"chunk_rows": c})) for c in (65536, 131072))
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    with torch.cuda.stream(s):
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    best = _lib.BatchConfig()
+    ms = ctypes.c_float(0)
+    _lib.check(lib.repro_batch_tune(arr, len(jobs), kt, vt, _T(T), _vp(ws), need, ctypes.byref(best),
+                                    ctypes.byref(ms), ctypes.c_void_p(s.cuda_stream)), "batch_tune")
+    return {"chunk_rows": best.chunk_rows, "max_slice_groups": best.max_slice_groups, "order": best.order}, ms.value

@@ -30,7 +30,7 @@ constexpr int64_t MAX_ROWS_PER_WG = (int64_t)1 << 23;
 constexpr size_t LDS_BIN_BUDGET = 150 * 1024;  // of gfx950's 160 KiB per workgroup
 constexpr size_t REPLICA_BUDGET = 32 * 1024;
 
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+__host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // LDS bin replicas for G groups at L levels: few groups get several copies
 // (lanes spread over them) to cut contention on the same words.
@@ -206,14 +206,15 @@ __device__ __forceinline__ void classify_rows(const KT* kc, const VT* vc, uint32
         const bool in = FULL || ((inr >> i) & 1u);
         const int64_t key = (int64_t)kc[i];
         const bool kok = (uint64_t)key < (uint64_t)(SLICE ? Gfull : (int64_t)G);
-        const bool ins = SLICE ? ((uint64_t)(key - glo) < (uint64_t)G) : kok;
+        // a valid key is below 2^31, so its offset in the slice fits 32 bits
+        const bool ins = SLICE ? (kok && (uint32_t)((uint32_t)key - (uint32_t)glo) < (uint32_t)G) : kok;
         const bool fin = finite_val(v);
         const bool nz = v != (VT)0;
         const int j = jreq_raw<AT>(frexp_raw(v));
         const bool dom = j <= Fmt<AT>::JMAX;
         const bool use = in && ins && fin && nz && dom;
         clean = clean && (!in || (kok && fin && (dom || !nz)));
-        gi[i] = use ? (int)(SLICE ? key - glo : key) : G;
+        gi[i] = use ? (int)(SLICE ? (uint32_t)key - (uint32_t)glo : (uint32_t)key) : G;
         ji[i] = use ? j : 0;
     }
 }

@@ -1,0 +1,525 @@
+// repro_batch.hip -- many independent GroupBy-SUM jobs in one persistent
+// launch (librepro, gfx950).
+//
+// Paper: Mueller, Arteaga, Hoefler, Alonso, "Reproducible Floating-Point
+// Aggregation in RDBMSs" (arXiv 1802.09883).  Every job is the GroupBy-SUM
+// of Sec. II-A into repro<T,L> (Sec. IV); its pieces are combined with
+// operator+=(repro) (the merge phase of Alg. 4), whose exact integer
+// arithmetic makes the bits independent of how the batch is cut and
+// scheduled.
+//
+// Work items are (job, row chunk, group slice).  A persistent grid of
+// 1024-thread workgroups takes items from a queue (one atomic counter) in
+// the order of a host-made table, largest items first.  An item aggregates
+// its chunk's rows of its slice's groups in LDS with the shared per-tile
+// loop (aggregate_range in slice mode), then either folds them straight
+// into the job's states (the job's only chunk) or writes a partial; the
+// last item of a (job, slice) to finish -- a device-scope counter -- folds
+// all partials of that slice into the states and, when asked, finalises.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "repro.h"
+#include "repro_agg.hpp"
+#include "repro_device.hpp"
+
+using namespace repro;
+
+namespace {
+
+constexpr int64_t BATCH_DEFAULT_CHUNK = 128 * 1024;
+constexpr int BATCH_MAX_CHUNKS = 1024;   // per job; chunks grow to stay below
+constexpr int BATCH_MAX_WG = 256;        // persistent workgroups: one per CU
+
+// Device record of a job (built by the planner).
+struct BatchJob {
+    const void* keys;
+    const void* vals;
+    void* states;
+    void* out;
+    long long n;
+    long long chunk;      // rows per chunk (multiple of the tile)
+    long long part_off;   // byte offset of this job's partials in the workspace
+    int G, L, accumulate, vec;
+    int nslices, gs, R;   // slices, groups per slice (the last may be smaller), LDS replicas
+    int nchunks;
+    int done_off;         // first completion counter of this job (one per slice)
+    int pad[3];
+};
+
+struct BatchItem {
+    int job, chunk, slice, pad;
+};
+
+// Workspace: [head][jobs][items][counters][partials], offsets in the head.
+struct BatchHead {
+    int next;  // queue position (reset by k_batch_reset)
+    int nitems;
+    int njobs;
+    int ncounters;
+    long long off_jobs, off_items, off_counters, off_partials;
+};
+
+struct BatchLayout {
+    size_t jobs, items, counters, partials, total;
+};
+
+inline BatchLayout batch_layout(int njobs, int64_t nitems, int64_t ncounters, size_t partial_bytes) {
+    BatchLayout b;
+    b.jobs = 256;
+    b.items = b.jobs + align_up((size_t)njobs * sizeof(BatchJob), 256);
+    b.counters = b.items + align_up((size_t)nitems * sizeof(BatchItem), 256);
+    b.partials = b.counters + align_up((size_t)ncounters * 4, 256);
+    b.total = b.partials + align_up(partial_bytes, 256);
+    return b;
+}
+
+// bytes of one (slice, chunk) partial: top[gs] int32, then K[L][gs] int64
+__host__ __device__ inline size_t partial_bytes(int gs, int L) { return align_up((size_t)gs * 4, 8) + (size_t)gs * L * 8; }
+
+template <class AT>
+__device__ __forceinline__ AT* S_ptr(void* st) {
+    return static_cast<AT*>(st);
+}
+template <class AT>
+__device__ __forceinline__ long long* C_ptr(void* st, int G, int L) {
+    return reinterpret_cast<long long*>(static_cast<unsigned char*>(st) + align_up((size_t)G * L * sizeof(AT), 8));
+}
+
+// Writes the canonical state of group g from (hi, lo) level words at top J,
+// and its finalised sum (equation of Sec. III-C) when `out` is given.
+template <class AT, int L>
+__device__ __forceinline__ void write_group(const long long* hi, const long long* lo, int J, AT* S, long long* C,
+                                            int G, int g, AT* out) {
+    typedef Fmt<AT> F;
+    AT q[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        long long cc, oo;
+        normalise<AT>(hi[l], lo[l], &cc, &oo);
+        S[(size_t)l * G + g] = make_S((AT*)0, F::B + (J - l) * F::W, oo);
+        C[(size_t)l * G + g] = cc;
+        if (out) {
+            const i128 K = (i128)cc * ((i128)1 << F::CARRY) + (i128)oo;
+            q[l] = round_exact<AT>(K, F::B + (J - l) * F::W - F::m);
+        }
+    }
+    if (out) {
+        AT acc = q[L - 1];
+#pragma unroll
+        for (int l = L - 2; l >= 0; --l) acc = acc + q[l];
+        out[g] = acc + (AT)0;
+    }
+}
+
+// Adds the level sums x[L] at top `top` to (hi, lo) words at top J >= top.
+template <class AT, int L>
+__device__ __forceinline__ void add_levels(const long long* x, int top, int J, long long* hi, long long* lo) {
+    constexpr int c = Fmt<AT>::CARRY;
+    const int d = J - top;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        long long v = 0;
+#pragma unroll
+        for (int q = 0; q < L; ++q) v = (q == l - d) ? x[q] : v;
+        hi[l] += v >> c;
+        lo[l] += v & ((1ll << c) - 1);
+    }
+}
+
+// Starts (hi, lo) level words at top J from the caller's state of group g
+// (C into hi, the low part of S into lo, moved down by J - top), or from
+// the empty state when the job overwrites.  Returns nothing: J must already
+// include the state's top (state_top_of).
+template <class AT, int L>
+__device__ __forceinline__ void start_from_state(const AT* S, const long long* C, int G, int g, bool use, int J,
+                                                 long long* hi, long long* lo) {
+#pragma unroll
+    for (int l = 0; l < L; ++l) hi[l] = lo[l] = 0;
+    if (!use) return;
+    const int d = J - state_top(S[g]);
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        if (l - d >= 0) {
+            hi[l] = C[(size_t)(l - d) * G + g];
+            lo[l] = state_lo(S[(size_t)(l - d) * G + g]);
+        }
+    }
+}
+
+template <class AT>
+__device__ __forceinline__ int state_top_of(const AT* S, int g, bool use, int L) {
+    return use ? state_top(S[g]) : L - 1;
+}
+
+// One item: aggregate, then fold or publish a partial; the last item of a
+// slice folds the slice.  Returns the lane's status bits.
+template <class KT, class VT, class AT, int L, int VEC>
+__device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned char* partials, int* counters,
+                             unsigned char* smem, AggShared& sh, int* s_last) {
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)bi.chunk * jb.chunk;
+    const int64_t r1 = min((int64_t)jb.n, r0 + jb.chunk);
+    const int64_t glo = (int64_t)bi.slice * jb.gs;
+    const int Gs = (int)min((int64_t)jb.gs, (int64_t)jb.G - glo);
+    const int R = jb.R;
+    const uint32_t err = aggregate_range<KT, VT, AT, L, VEC, false, true>(
+        static_cast<const KT*>(jb.keys), static_cast<const VT*>(jb.vals), r0, r1, Gs, R, smem, sh, nullptr, glo,
+        jb.G);
+    const long long* bins = reinterpret_cast<const long long*>(smem);
+    const int2* TOP = reinterpret_cast<const int2*>(bins + (size_t)(Gs + 1) * R * L);
+    AT* S = S_ptr<AT>(jb.states);
+    long long* C = C_ptr<AT>(jb.states, jb.G, L);
+    AT* out = static_cast<AT*>(jb.out);
+    auto level_sums = [&](int g, long long* x) {
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            long long s = 0;
+            for (int r = 0; r < R; ++r) s += bins[((size_t)l * (Gs + 1) + g) * R + r];
+            x[l] = s;
+        }
+    };
+    if (jb.nchunks == 1) {
+        for (int g = tid; g < Gs; g += AGG_BLOCK) {
+            const int gg = (int)glo + g;
+            long long x[L], hi[L], lo[L];
+            level_sums(g, x);
+            const int J = max(TOP[g].x, state_top_of(S, gg, jb.accumulate, L));
+            start_from_state<AT, L>(S, C, jb.G, gg, jb.accumulate, J, hi, lo);
+            add_levels<AT, L>(x, TOP[g].x, J, hi, lo);
+            write_group<AT, L>(hi, lo, J, S, C, jb.G, gg, out);
+        }
+        __syncthreads();  // LDS is reused by the next item
+        return err;
+    }
+    // publish this chunk's partial of the slice
+    const size_t pbytes = partial_bytes(jb.gs, L);
+    unsigned char* part0 = partials + jb.part_off + (size_t)bi.slice * jb.nchunks * pbytes;
+    {
+        unsigned char* pp = part0 + (size_t)bi.chunk * pbytes;
+        int* ptop = reinterpret_cast<int*>(pp);
+        long long* pK = reinterpret_cast<long long*>(pp + align_up((size_t)jb.gs * 4, 8));
+        for (int g = tid; g < Gs; g += AGG_BLOCK) {
+            long long x[L];
+            level_sums(g, x);
+            ptop[g] = TOP[g].x;
+#pragma unroll
+            for (int l = 0; l < L; ++l) pK[(size_t)l * jb.gs + g] = x[l];
+        }
+    }
+    __threadfence();  // this thread's partial words visible device-wide before the count
+    __syncthreads();
+    if (tid == 0) *s_last = (atomicAdd(&counters[jb.done_off + bi.slice], 1) == jb.nchunks - 1);
+    __syncthreads();
+    if (*s_last) {
+        __threadfence();  // see the other items' partials
+        for (int g = tid; g < Gs; g += AGG_BLOCK) {
+            const int gg = (int)glo + g;
+            long long hi[L], lo[L];
+            int J = state_top_of(S, gg, jb.accumulate, L);
+            for (int c = 0; c < jb.nchunks; ++c)
+                J = max(J, reinterpret_cast<const int*>(part0 + (size_t)c * pbytes)[g]);
+            start_from_state<AT, L>(S, C, jb.G, gg, jb.accumulate, J, hi, lo);
+            for (int c = 0; c < jb.nchunks; ++c) {
+                const unsigned char* pp = part0 + (size_t)c * pbytes;
+                const long long* pK = reinterpret_cast<const long long*>(pp + align_up((size_t)jb.gs * 4, 8));
+                long long x[L];
+#pragma unroll
+                for (int l = 0; l < L; ++l) x[l] = pK[(size_t)l * jb.gs + g];
+                add_levels<AT, L>(x, reinterpret_cast<const int*>(pp)[g], J, hi, lo);
+            }
+            write_group<AT, L>(hi, lo, J, S, C, jb.G, gg, out);
+        }
+    }
+    __syncthreads();
+    return err;
+}
+
+template <class KT, class VT, class AT, int L>
+__device__ __forceinline__ uint32_t run_item_vec(const BatchJob& jb, const BatchItem& bi, unsigned char* partials,
+                                                 int* counters, unsigned char* smem, AggShared& sh, int* s_last) {
+    constexpr int VEC = 16 / sizeof(VT);
+    if (jb.vec) return run_item<KT, VT, AT, L, VEC>(jb, bi, partials, counters, smem, sh, s_last);
+    return run_item<KT, VT, AT, L, 1>(jb, bi, partials, counters, smem, sh, s_last);
+}
+
+// Zeroes the queue position and the completion counters (a kernel, so that
+// the launch can be captured into a graph without memset nodes).
+__global__ void __launch_bounds__(256) k_batch_reset(unsigned char* __restrict__ ws) {
+    BatchHead* hd = reinterpret_cast<BatchHead*>(ws);
+    int* counters = reinterpret_cast<int*>(ws + hd->off_counters);
+    const int nc = hd->ncounters;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < nc; i += gridDim.x * 256) counters[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) hd->next = 0;
+}
+
+// The persistent kernel: every workgroup takes items until the queue is
+// empty (each loop iteration advances the shared position by one, so every
+// workgroup reaches the exit).
+template <class KT, class VT, class AT>
+__global__ void __launch_bounds__(AGG_BLOCK) k_batch(unsigned char* __restrict__ ws, uint32_t* __restrict__ status) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ AggShared sh;
+    __shared__ int s_item, s_last;
+    BatchHead* hd = reinterpret_cast<BatchHead*>(ws);
+    const BatchJob* jobs = reinterpret_cast<const BatchJob*>(ws + hd->off_jobs);
+    const BatchItem* items = reinterpret_cast<const BatchItem*>(ws + hd->off_items);
+    int* counters = reinterpret_cast<int*>(ws + hd->off_counters);
+    unsigned char* partials = ws + hd->off_partials;
+    const int nitems = hd->nitems;
+    uint32_t err = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&hd->next, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);  // uniform: job records load as scalars
+        __syncthreads();  // every thread has read s_item before it changes
+        if (it >= nitems) break;
+        const BatchItem bi = items[it];
+        const BatchJob jb = jobs[bi.job];
+        switch (jb.L) {
+            case 1: err |= run_item_vec<KT, VT, AT, 1>(jb, bi, partials, counters, smem, sh, &s_last); break;
+            case 2: err |= run_item_vec<KT, VT, AT, 2>(jb, bi, partials, counters, smem, sh, &s_last); break;
+            case 3: err |= run_item_vec<KT, VT, AT, 3>(jb, bi, partials, counters, smem, sh, &s_last); break;
+            default: err |= run_item_vec<KT, VT, AT, 4>(jb, bi, partials, counters, smem, sh, &s_last); break;
+        }
+    }
+    report(status, err);
+}
+
+// ---------------------------------------------------------------- host
+
+inline size_t scalar_bytes(repro_scalar_t t) { return t == REPRO_F64 ? 8 : 4; }
+
+struct HostPlan {
+    std::vector<BatchJob> jobs;
+    std::vector<BatchItem> items;
+    int64_t ncounters = 0;
+    size_t partial_bytes = 0;
+    size_t lds = 0;
+    BatchLayout lay{};
+};
+
+bool valid_types(repro_key_t kt, repro_scalar_t vt, repro_scalar_t T) {
+    if (kt != REPRO_I32 && kt != REPRO_I64) return false;
+    if (vt != REPRO_F32 && vt != REPRO_F64) return false;
+    if (T != REPRO_F32 && T != REPRO_F64) return false;
+    return !(vt == REPRO_F64 && T == REPRO_F32);  // narrowing is not exact
+}
+
+// Largest slice (groups) whose LDS bins fit, under the configured cap.
+int slice_cap(int L, int cap_cfg) {
+    int g = (int)(LDS_BIN_BUDGET / (size_t)(8 * L + 12)) - 1;
+    while (g > 1 && agg_lds_bytes(g, L, 1) > LDS_BIN_BUDGET) --g;
+    if (cap_cfg > 0 && cap_cfg < g) g = cap_cfg;
+    return g;
+}
+
+bool make_batch_plan(const repro_batch_job* jobs, int njobs, repro_key_t kt, repro_scalar_t vt, repro_scalar_t T,
+                     const repro_batch_config* cfg, HostPlan* hp) {
+    if (njobs < 0 || (njobs > 0 && !jobs) || !valid_types(kt, vt, T)) return false;
+    int64_t chunk_cfg = (cfg && cfg->chunk_rows > 0) ? cfg->chunk_rows : BATCH_DEFAULT_CHUNK;
+    chunk_cfg = (chunk_cfg + AGG_TILE - 1) / AGG_TILE * AGG_TILE;
+    const int cap_cfg = cfg ? cfg->max_slice_groups : 0;
+    const int order = cfg ? cfg->order : 0;
+    if (order != 0 && order != 1) return false;
+    const size_t ksz = kt == REPRO_I64 ? 8 : 4, vsz = scalar_bytes(vt);
+    hp->jobs.resize(njobs);
+    hp->items.clear();
+    hp->ncounters = 0;
+    hp->partial_bytes = 0;
+    hp->lds = 0;
+    std::vector<int64_t> cost;
+    for (int j = 0; j < njobs; ++j) {
+        const repro_batch_job& u = jobs[j];
+        if (u.n < 0 || u.n > INT32_MAX || u.num_groups < 1 || u.num_groups > INT32_MAX || u.L < 1 || u.L > 4 ||
+            !u.states || (u.n > 0 && (!u.keys || !u.values)) || (u.accumulate != 0 && u.accumulate != 1))
+            return false;
+        BatchJob& b = hp->jobs[j];
+        memset(&b, 0, sizeof(b));
+        b.keys = u.keys;
+        b.vals = u.values;
+        b.states = u.states;
+        b.out = u.out;
+        b.n = u.n;
+        b.G = (int)u.num_groups;
+        b.L = u.L;
+        b.accumulate = u.accumulate;
+        b.vec = ((uintptr_t)u.keys % (16 / vsz * ksz) == 0) && ((uintptr_t)u.values % 16 == 0);
+        const int cap = slice_cap(u.L, cap_cfg);
+        b.nslices = (int)((u.num_groups + cap - 1) / cap);
+        b.gs = (int)((u.num_groups + b.nslices - 1) / b.nslices);
+        b.R = b.nslices == 1 ? replicas_for(b.gs, u.L) : 1;
+        hp->lds = std::max(hp->lds, agg_lds_bytes(b.gs, u.L, b.R));
+        // chunks: the configured size, larger when the job would need too many;
+        // at most 2^23 rows each (bin words stay below 2^62)
+        int64_t chunk = chunk_cfg;
+        const int64_t need = (u.n + BATCH_MAX_CHUNKS - 1) / BATCH_MAX_CHUNKS;
+        if (chunk < need) chunk = (need + AGG_TILE - 1) / AGG_TILE * AGG_TILE;
+        if (chunk > MAX_ROWS_PER_WG) chunk = MAX_ROWS_PER_WG;
+        b.chunk = chunk;
+        // a job without rows still gets one item per slice: it writes the
+        // (empty, or unchanged) states and the finalised sums
+        b.nchunks = u.n > 0 ? (int)((u.n + chunk - 1) / chunk) : 1;
+        if (b.nchunks > 1) {
+            b.done_off = (int)hp->ncounters;
+            hp->ncounters += b.nslices;
+            b.part_off = (long long)hp->partial_bytes;
+            hp->partial_bytes += align_up((size_t)b.nslices * b.nchunks * partial_bytes(b.gs, u.L), 256);
+        }
+        for (int c = 0; c < b.nchunks; ++c)
+            for (int s = 0; s < b.nslices; ++s) {
+                hp->items.push_back(BatchItem{j, c, s, 0});
+                cost.push_back(std::min<int64_t>(chunk, u.n - (int64_t)c * chunk));
+            }
+    }
+    if (hp->items.size() > (size_t)INT32_MAX / 2 || hp->ncounters > INT32_MAX / 2) return false;
+    if (order == 0) {
+        // largest first; the slices of one chunk stay together (they read the same rows)
+        std::vector<int> idx(hp->items.size());
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        std::vector<BatchItem> sorted(idx.size());
+        for (size_t i = 0; i < idx.size(); ++i) sorted[i] = hp->items[idx[i]];
+        hp->items.swap(sorted);
+    }
+    hp->lay = batch_layout(njobs, (int64_t)hp->items.size(), hp->ncounters, hp->partial_bytes);
+    return true;
+}
+
+template <class KT, class VT, class AT>
+const void* batch_kernel() {
+    return reinterpret_cast<const void*>(k_batch<KT, VT, AT>);
+}
+
+const void* pick_kernel(int kt, int vt, int T) {
+    if (kt == REPRO_I32) {
+        if (vt == REPRO_F32) return T == REPRO_F32 ? batch_kernel<int32_t, float, float>() : batch_kernel<int32_t, float, double>();
+        return batch_kernel<int32_t, double, double>();
+    }
+    if (vt == REPRO_F32) return T == REPRO_F32 ? batch_kernel<int64_t, float, float>() : batch_kernel<int64_t, float, double>();
+    return batch_kernel<int64_t, double, double>();
+}
+
+int launch_plan(const repro_batch_plan* p, uint32_t* status, hipStream_t st) {
+    unsigned char* ws = static_cast<unsigned char*>(p->workspace);
+    hipLaunchKernelGGL(k_batch_reset, dim3(64), dim3(256), 0, st, ws);
+    if (hipGetLastError() != hipSuccess) return REPRO_EHIP;
+    if (p->items == 0) return REPRO_OK;
+    const void* fn = pick_kernel(p->kt, p->vt, p->T);  // its LDS limit was raised by the prepare call
+    void* args[] = {&ws, &status};
+    if (hipLaunchKernel(fn, dim3(p->grid), dim3(AGG_BLOCK), args, (size_t)p->lds_bytes, st) != hipSuccess)
+        return REPRO_EHIP;
+    return REPRO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t repro_batch_workspace_bytes(const repro_batch_job* jobs, int njobs, repro_key_t kt, repro_scalar_t vt,
+                                   repro_scalar_t T, const repro_batch_config* cfg) {
+    HostPlan hp;
+    if (!make_batch_plan(jobs, njobs, kt, vt, T, cfg, &hp)) return 0;
+    return hp.lay.total;
+}
+
+int repro_batch_prepare(const repro_batch_job* jobs, int njobs, repro_key_t kt, repro_scalar_t vt, repro_scalar_t T,
+                        const repro_batch_config* cfg, void* workspace, size_t workspace_bytes,
+                        repro_batch_plan* plan, hipStream_t stream) {
+    if (!plan) return REPRO_EINVAL;
+    HostPlan hp;
+    if (!make_batch_plan(jobs, njobs, kt, vt, T, cfg, &hp)) return REPRO_EINVAL;
+    if (!workspace || workspace_bytes < hp.lay.total || (uintptr_t)workspace % 256 != 0) return REPRO_EINVAL;
+    // the plan image: head, jobs, items (counters and partials are device-only)
+    std::vector<unsigned char> img(hp.lay.counters, 0);
+    BatchHead hd;
+    memset(&hd, 0, sizeof(hd));
+    hd.nitems = (int)hp.items.size();
+    hd.njobs = njobs;
+    hd.ncounters = (int)hp.ncounters;
+    hd.off_jobs = (long long)hp.lay.jobs;
+    hd.off_items = (long long)hp.lay.items;
+    hd.off_counters = (long long)hp.lay.counters;
+    hd.off_partials = (long long)hp.lay.partials;
+    memcpy(img.data(), &hd, sizeof(hd));
+    if (njobs) memcpy(img.data() + hp.lay.jobs, hp.jobs.data(), hp.jobs.size() * sizeof(BatchJob));
+    if (!hp.items.empty()) memcpy(img.data() + hp.lay.items, hp.items.data(), hp.items.size() * sizeof(BatchItem));
+    if (hipMemcpyAsync(workspace, img.data(), img.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
+        return REPRO_EHIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return REPRO_EHIP;
+    // dynamic LDS beyond 64 KiB must be allowed per kernel; done here, outside
+    // any graph capture of the launches
+    if (hp.lds > 64 * 1024 && hipFuncSetAttribute(pick_kernel(kt, vt, T), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  (int)hp.lds) != hipSuccess)
+        return REPRO_EHIP;
+    memset(plan, 0, sizeof(*plan));
+    plan->workspace = workspace;
+    plan->items = (int64_t)hp.items.size();
+    plan->grid = (int)std::min<int64_t>(BATCH_MAX_WG, std::max<int64_t>(1, plan->items));
+    plan->lds_bytes = (int)hp.lds;
+    plan->kt = kt;
+    plan->vt = vt;
+    plan->T = T;
+    return REPRO_OK;
+}
+
+int repro_batch_launch(const repro_batch_plan* plan, uint32_t* status, hipStream_t stream) {
+    if (!plan || !plan->workspace || plan->items < 0 || !valid_types((repro_key_t)plan->kt, (repro_scalar_t)plan->vt,
+                                                                      (repro_scalar_t)plan->T))
+        return REPRO_EINVAL;
+    return launch_plan(plan, status, stream);
+}
+
+int repro_batch_tune(const repro_batch_job* jobs, int njobs, repro_key_t kt, repro_scalar_t vt, repro_scalar_t T,
+                     void* workspace, size_t workspace_bytes, repro_batch_config* best, float* best_ms,
+                     hipStream_t stream) {
+    if (!best) return REPRO_EINVAL;
+    const int64_t chunks[] = {65536, 131072, 262144, 524288};
+    const int caps[] = {0, 1024};
+    const int orders[] = {0, 1};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return REPRO_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return REPRO_EHIP;
+    }
+    float best_t = -1.0f;
+    int rc = REPRO_OK;
+    for (int64_t ch : chunks)
+        for (int cap : caps)
+            for (int ord : orders) {
+                repro_batch_config c{ch, cap, ord};
+                if (repro_batch_workspace_bytes(jobs, njobs, kt, vt, T, &c) > workspace_bytes) continue;
+                repro_batch_plan p;
+                rc = repro_batch_prepare(jobs, njobs, kt, vt, T, &c, workspace, workspace_bytes, &p, stream);
+                if (rc != REPRO_OK) goto done;
+                if ((rc = launch_plan(&p, nullptr, stream)) != REPRO_OK) goto done;  // warm-up
+                if (hipEventRecord(e0, stream) != hipSuccess) { rc = REPRO_EHIP; goto done; }
+                for (int r = 0; r < 2; ++r)
+                    if ((rc = launch_plan(&p, nullptr, stream)) != REPRO_OK) goto done;
+                if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                    rc = REPRO_EHIP;
+                    goto done;
+                }
+                float ms = 0;
+                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = REPRO_EHIP; goto done; }
+                ms *= 0.5f;
+                if (best_t < 0 || ms < best_t) {
+                    best_t = ms;
+                    *best = c;
+                }
+            }
+done:
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != REPRO_OK) return rc;
+    if (best_t < 0) return REPRO_EINVAL;  // no candidate fits the workspace
+    if (best_ms) *best_ms = best_t;
+    return REPRO_OK;
+}
+
+}  // extern "C"

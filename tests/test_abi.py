@@ -56,3 +56,36 @@ def test_invalid_arguments_return_einval_without_gpu(lib):
     assert lib.repro_groupby_sum(null, 0, null, 1, 0, 4, 1, 2, p, null, 0, null, null) == _lib.REPRO_OK
     assert lib.repro_merge(p, p, 4, 1, 2, null) == _lib.REPRO_EINVAL
     assert lib.repro_finalize(p, 4, 1, 2, null, null) == _lib.REPRO_EINVAL
+
+
+def _jobs(specs):
+    """Host job records with fake device addresses (the planner never
+    dereferences them)."""
+    arr = (_lib.BatchJob * len(specs))()
+    for i, (n, G, L) in enumerate(specs):
+        arr[i] = _lib.BatchJob(0x10000 * (i + 1), 0x20000000 + 0x10000 * i, n, G, L, 0, 0x40000000 + 0x1000 * i, None)
+    return arr
+
+
+def test_batch_workspace_and_validation_without_gpu(lib):
+    ok = [(1000, 16, 2), (0, 5, 3), (2_000_000, 70_000, 3), (300_000, 4000, 1)]
+    jobs = _jobs(ok)
+    need = lib.repro_batch_workspace_bytes(jobs, len(ok), _lib.I32, _lib.F64, _lib.F64, None)
+    assert need > 0 and need % 256 == 0
+    # the partial sums of split jobs grow with the number of chunks
+    small = _lib.BatchConfig(1 << 20, 0, 0)
+    assert lib.repro_batch_workspace_bytes(jobs, len(ok), _lib.I32, _lib.F64, _lib.F64, ctypes.byref(small)) < need
+    for bad in ([(10, 0, 2)], [(10, 4, 0)], [(10, 4, 5)], [(-1, 4, 2)]):
+        assert lib.repro_batch_workspace_bytes(_jobs(bad), 1, _lib.I32, _lib.F64, _lib.F64, None) == 0
+    assert lib.repro_batch_workspace_bytes(jobs, len(ok), _lib.I32, _lib.F64, _lib.F32, None) == 0  # narrowing
+    nostate = _jobs([(10, 4, 2)])
+    nostate[0].states = None
+    assert lib.repro_batch_workspace_bytes(nostate, 1, _lib.I32, _lib.F64, _lib.F64, None) == 0
+    plan = _lib.BatchPlan()
+    # invalid arguments are rejected before anything touches the GPU
+    assert lib.repro_batch_prepare(_jobs([(10, 4, 5)]), 1, _lib.I32, _lib.F64, _lib.F64, None, ctypes.c_void_p(256),
+                                   1 << 20, ctypes.byref(plan), None) == _lib.REPRO_EINVAL
+    assert lib.repro_batch_prepare(jobs, len(ok), _lib.I32, _lib.F64, _lib.F64, None, ctypes.c_void_p(256), need - 1,
+                                   ctypes.byref(plan), None) == _lib.REPRO_EINVAL
+    assert lib.repro_batch_prepare(jobs, len(ok), _lib.I32, _lib.F64, _lib.F64, None, ctypes.c_void_p(257), need,
+                                   ctypes.byref(plan), None) == _lib.REPRO_EINVAL

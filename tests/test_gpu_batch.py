@@ -1,0 +1,200 @@
+"""Batched GroupBy-SUM (many independent jobs in one persistent launch):
+bit-exact parity of every job with the CPU oracle, independence of the
+configuration and schedule, graph capture and the autotuner (needs a GPU)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1802_09883_amd import workloads as WL
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1802_09883_amd import api
+else:  # collected on CPU-only hosts, never run there
+    api = None
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def mixed_jobs(seed, count, max_rows=400_000, max_groups=70_000, errors=True):
+    """Jobs of uneven sizes: rows log-uniform (some empty), groups log-uniform
+    (several beyond one workgroup's LDS, so cut into group slices), L 1..4."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(count):
+        n = 0 if j % 11 == 3 else int(np.exp(rng.uniform(np.log(50), np.log(max_rows))))
+        G = int(np.exp(rng.uniform(0, np.log(max_groups))))
+        L = int(rng.integers(1, 5))
+        keys = rng.integers(0, G, n).astype(np.int32)
+        vals = np.ldexp(rng.standard_normal(n), rng.integers(-30, 31, n))
+        if errors and j % 7 == 5 and n > 10:
+            keys[::97] = G + 3
+            vals[5] = np.nan
+        out.append((keys, vals, G, L))
+    return out
+
+
+def oracle_job(keys, vals, G, L, prior=None):
+    st, status = O.groupby_sum(keys, vals, G, L, True, threads=8)
+    if prior is not None:
+        st = O.merge(prior, st, G, L, True)
+    return st, status
+
+
+def make_batch(specs, accumulate=None, with_out=True):
+    jobs, priors = [], []
+    for i, (keys, vals, G, L) in enumerate(specs):
+        acc = bool(accumulate and accumulate(i))
+        prior = None
+        if acc:
+            # earlier rows of this group set, already in the states
+            rng = np.random.default_rng(1000 + i)
+            pk = rng.integers(0, G, 3000).astype(np.int32)
+            pv = np.ldexp(rng.standard_normal(3000), rng.integers(-60, 61, 3000))
+            st = api.groupby_sum(dev(pk), dev(pv), G, L)
+            prior = O.groupby_sum(pk, pv, G, L)[0]
+        else:
+            st = torch.full((api.state_bytes(G, L),), 0xAB, dtype=torch.uint8, device="cuda")  # overwritten
+        out = torch.full((G,), float("nan"), dtype=torch.float64, device="cuda") if with_out else None
+        jobs.append(api.Job(dev(keys), dev(vals), G, L, st, out, accumulate=acc))
+        priors.append(prior)
+    return jobs, priors
+
+
+def check_jobs(jobs, specs, priors, status, what):
+    want_status = 0
+    for i, (job, (keys, vals, G, L), prior) in enumerate(zip(jobs, specs, priors)):
+        ref, st = oracle_job(keys, vals, G, L, prior)
+        want_status |= st
+        got = job.states.cpu().numpy()
+        Sg, Cg = O.split_states(got, G, L, True)
+        So, Co = O.split_states(ref, G, L, True)
+        assert np.array_equal(Sg.view(np.uint8), So.view(np.uint8)) and np.array_equal(Cg, Co), \
+            f"{what}: job {i} (n={len(keys)}, G={G}, L={L}) states differ from the oracle"
+        if job.out is not None:
+            assert np.array_equal(job.out.cpu().numpy().view(np.uint8), O.finalize(ref, G, L).view(np.uint8)), \
+                f"{what}: job {i} finalised sums differ"
+    assert status == want_status, f"{what}: status {status} vs oracle {want_status}"
+
+
+def test_batch_matches_oracle_per_job():
+    specs = mixed_jobs(1, 40)
+    say(f"case batch of {len(specs)} mixed jobs, {sum(len(s[0]) for s in specs)} rows")
+    jobs, priors = make_batch(specs, accumulate=lambda i: i % 3 == 1)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    api.batch_groupby_sum(jobs, status=status)
+    torch.cuda.synchronize()
+    check_jobs(jobs, specs, priors, int(status.item()), "mixed batch")
+
+
+@pytest.mark.parametrize("config", [
+    {"chunk_rows": 8192}, {"chunk_rows": 1 << 20}, {"max_slice_groups": 300}, {"order": 1},
+    {"chunk_rows": 16384, "max_slice_groups": 1000, "order": 1}])
+def test_batch_configuration_does_not_change_bits(config):
+    specs = mixed_jobs(2, 24, max_rows=200_000, errors=False)
+    say(f"case batch config {config}")
+    jobs, priors = make_batch(specs)
+    run = api.batch_groupby_sum(jobs, config=config)
+    torch.cuda.synchronize()
+    check_jobs(jobs, specs, priors, 0, f"config {config}")
+    # launching the same plan again (overwrite mode) gives the same bits
+    before = [j.states.clone() for j in jobs]
+    api.batch_launch(run)
+    torch.cuda.synchronize()
+    for a, j in zip(before, jobs):
+        assert torch.equal(a, j.states)
+
+
+def test_batch_accumulating_launches_add_the_batch_each_time():
+    specs = mixed_jobs(3, 10, max_rows=50_000, errors=False)
+    jobs, _ = make_batch(specs, with_out=False)
+    for j in jobs:
+        j.states = api.state_init(j.num_groups, j.L)
+        j.accumulate = True
+    run = api.batch_prepare(jobs)
+    api.batch_launch(run)
+    api.batch_launch(run)
+    torch.cuda.synchronize()
+    for j, (keys, vals, G, L) in zip(jobs, specs):
+        ref, _ = O.groupby_sum(np.concatenate([keys, keys]), np.concatenate([vals, vals]), G, L)
+        assert np.array_equal(j.states.cpu().numpy(), ref)
+
+
+def test_batch_graph_capture_and_replay():
+    specs = mixed_jobs(4, 16, max_rows=100_000, errors=False)
+    jobs, priors = make_batch(specs)
+    run = api.batch_prepare(jobs)
+    api.batch_launch(run)
+    torch.cuda.synchronize()
+    eager = [j.states.clone() for j in jobs]
+    outs = [j.out.clone() for j in jobs]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        api.batch_launch(run, stream=s)
+    for rep in range(3):
+        for j in jobs:  # eager work between replays: scribble over the results
+            j.states.fill_(0x5A)
+            j.out.fill_(1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, j in enumerate(jobs):
+            assert torch.equal(j.states, eager[i]), f"replay {rep}: job {i} states differ from the eager launch"
+            assert torch.equal(j.out, outs[i]), f"replay {rep}: job {i} sums differ"
+    check_jobs(jobs, specs, priors, 0, "graph replay")
+
+
+def test_batch_autotuner_result_is_bit_neutral():
+    specs = mixed_jobs(5, 20, max_rows=300_000, errors=False)
+    jobs, priors = make_batch(specs)
+    best, ms = api.batch_tune(jobs)
+    say(f"tuned config {best}, {ms:.3f} ms")
+    assert ms > 0 and best["chunk_rows"] > 0 and best["order"] in (0, 1)
+    for j in jobs:
+        j.states.fill_(0)
+    api.batch_groupby_sum(jobs, config=best)
+    torch.cuda.synchronize()
+    check_jobs(jobs, specs, priors, 0, "tuned config")
+
+
+def test_batch_invalid_jobs_are_rejected():
+    k = dev(np.zeros(10, np.int32))
+    v = dev(np.zeros(10))
+    st = api.state_init(4, 2)
+    for bad in (dict(L=0), dict(L=5), dict(num_groups=0)):
+        args = dict(keys=k, values=v, num_groups=4, L=2, states=st)
+        args.update(bad)
+        with pytest.raises(ValueError):
+            api.batch_prepare([api.Job(**args)])
+    with pytest.raises(ValueError):
+        api.batch_prepare([api.Job(k, dev(np.zeros(10)), 4, 2, st)], T=torch.float32)  # f64 -> float narrows
+
+
+def test_batch_full_size_512_jobs_sampled():
+    """The batched workload at its full size (512 jobs, rows log-uniform
+    1e3..1e7, groups log-uniform 1..2^16, L in {2, 3}); every 8th job and
+    the largest ones are checked against the oracle."""
+    rows, groups, Ls = WL.batched_jobs()
+    say(f"case full batch: {len(rows)} jobs, {int(rows.sum())} rows")
+    specs = [(*WL.batched_job(int(r), int(g), j), int(g), int(l)) for j, (r, g, l) in enumerate(zip(rows, groups, Ls))]
+    jobs, priors = make_batch(specs, with_out=False)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    api.batch_groupby_sum(jobs, status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    pick = sorted(set(range(0, len(jobs), 8)) | set(np.argsort(rows)[-4:].tolist()) |
+                  set(np.argsort(groups)[-4:].tolist()))
+    check_jobs([jobs[i] for i in pick], [specs[i] for i in pick], [priors[i] for i in pick], 0, "full batch")

@@ -108,14 +108,20 @@ def test_shapes_and_levels(L, kdt, n):
     check_case(keys, vals.astype(np.float32), G, L, False, "shapes f32 acc")
 
 
+# largest group count whose bins fit one workgroup's LDS: (G + 1) * (8L + 12)
+# bytes within 150 KiB; one more group takes the partitioned path
+LDS_MAX_G = {1: 7679, 2: 5484, 3: 4265, 4: 3489}
+
+
 @pytest.mark.parametrize("L", [1, 2, 3, 4])
-def test_largest_lds_group_count(L):
-    G = {1: 3200, 2: 2300, 3: 1800, 4: 1480}[L]
-    rng = np.random.default_rng(L)
+@pytest.mark.parametrize("extra", [0, 1])
+def test_largest_lds_group_count(L, extra):
+    G = LDS_MAX_G[L] + extra
+    rng = np.random.default_rng([L, extra])
     n = 300_000
     keys = rng.integers(0, G, n).astype(np.int32)
     vals = np.ldexp(rng.standard_normal(n), rng.integers(-40, 40, n))
-    check_case(keys, vals, G, L, True, "largest LDS G")
+    check_case(keys, vals, G, L, True, "largest LDS G" if extra == 0 else "one group beyond LDS")
 
 
 def test_misaligned_columns_take_scalar_loads():
