@@ -253,10 +253,10 @@ def bench_batched(args):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(s)
+    e0.record()  # replay() launches the graph on the current stream
     for _ in range(args.steps):
         g.replay()
-    e1.record(s)
+    e1.record()
     torch.cuda.synchronize()
     ms_step = (time.perf_counter() - t0) * 1000.0 / args.steps
     ms_dev = e0.elapsed_time(e1) / args.steps

@@ -115,8 +115,8 @@ __device__ __forceinline__ void report(uint32_t* status, uint32_t err) {
 
 // ------------------------------------------------------ the hot kernel
 //
-// LDS layout (G real groups plus one trash slot G that absorbs skipped
-// rows, so the deposit loop has no per-row branch):
+// LDS layout (G real groups plus one trash slot G that takes the rows a
+// workgroup skips, so that every row has a slot and a top):
 //   bins[L][G+1][R]  int64 level sums; lane r deposits into replica r % R
 //                    (R > 1 only when groups are few, to spread contention).
 //                    Level-major, so that the words one level-add of a wave
@@ -127,12 +127,27 @@ __device__ __forceinline__ void report(uint32_t* status, uint32_t err) {
 //   P[G+1]           pending top, raised with ds_max while a tile is read
 // A workgroup-uniform fast path applies while every group sits at the same
 // top Ju ("uni"): then no per-row LDS read of the top is needed.
+constexpr int RAISED_MAX = 1024;  // groups listed per synchronisation (beyond: a full scan)
+
 struct AggShared {
     int newmax;     // largest top after a realignment
     int cnt;        // groups at newmax
     int flag[3];    // "some top was raised" per synchronisation (3 rotating slots)
     int spills[3];  // rows deposited into the spill array, per synchronisation
+    int nraised[3]; // groups whose pending top rose, per synchronisation
+    int raised[RAISED_MAX];  // those groups (each once), for the realignment
 };
+
+// Raises the pending top of group g to j (j > cur, the group's top since the
+// last synchronisation).  The lane whose atomic max lifts P from cur lists
+// the group, so every raised group is listed exactly once per interval.
+__device__ __forceinline__ void raise_top(int* P, int g, int j, int cur, AggShared& sh, int slot) {
+    const int old = atomicMax(&P[g], j);
+    if (old == cur) {
+        const int k = atomicAdd(&sh.nraised[slot], 1);
+        if (k < RAISED_MAX) sh.raised[k] = g;
+    }
+}
 
 __device__ __forceinline__ uint32_t extractor_hi_of(double*, int top) {
     return extractor_hi((double*)0, Fmt<double>::B + top * Fmt<double>::W);
@@ -268,11 +283,12 @@ constexpr int QUIET_TILES = 1;   // quiet per-tile synchronisations before epoch
 // enables epoch mode, which needs the spill array, and the tracking of a
 // top shared by all groups (few groups, whose tops settle early); without
 // it every tile synchronises and rows read their group's top from LDS.
-template <class KT, class VT, class AT, int L, int VEC, bool EPOCH, bool SLICE = false>
+template <class KT, class VT, class AT, int L, int VEC, bool EPOCH, bool SLICE = false, int BLOCK = AGG_BLOCK>
 __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys, const VT* __restrict__ vals,
                                                     int64_t c0, int64_t c1, int G, int R, unsigned char* smem,
                                                     AggShared& sh, unsigned long long* __restrict__ spill,
                                                     int64_t glo = 0, int64_t Gfull = 0) {
+    constexpr int TILE = BLOCK * ROWS_PER_THREAD;  // rows of one tile
     typedef Fmt<AT> F;
     constexpr int U = ROWS_PER_THREAD / VEC;
     long long* bins = reinterpret_cast<long long*>(smem);
@@ -284,9 +300,9 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
     const uint32_t gstride = (uint32_t)(R * 8);             // bytes per group in a level
     const uint32_t lstride = (uint32_t)((G + 1) * R * 8);   // bytes per level
     const uint32_t lane_off = (uint32_t)(rep * 8);
-    for (int i = tid; i < (G + 1) * R * L; i += AGG_BLOCK) bins[i] = 0;
+    for (int i = tid; i < (G + 1) * R * L; i += BLOCK) bins[i] = 0;
     const uint32_t h_init = extractor_hi_of((AT*)0, L - 1);
-    for (int i = tid; i < G; i += AGG_BLOCK) {
+    for (int i = tid; i < G; i += BLOCK) {
         TOP[i] = make_int2(L - 1, (int)h_init);
         P[i] = L - 1;
     }
@@ -295,7 +311,7 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
         P[G] = F::JMAX;
         sh.newmax = L - 1;
         sh.cnt = G;
-        for (int q = 0; q < 3; ++q) sh.flag[q] = sh.spills[q] = 0;
+        for (int q = 0; q < 3; ++q) sh.flag[q] = sh.spills[q] = sh.nraised[q] = 0;
     }
     __syncthreads();
 
@@ -317,16 +333,18 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
         __syncthreads();
         const int f = sh.flag[sync % 3];
         spilled = sh.spills[sync % 3];
+        const int nr = sh.nraised[sync % 3];
         if (tid == 0) {  // slot (sync+2)%3 was read at the previous synchronisation
             sh.flag[(sync + 2) % 3] = 0;   // and is next written after the following one
             sh.spills[(sync + 2) % 3] = 0;
+            sh.nraised[(sync + 2) % 3] = 0;
         }
         ++sync;
         if (!f) return false;
-        int m = -1;
-        for (int g = tid; g < G; g += AGG_BLOCK) {
+        int m = -1;  // largest realigned top (the others did not move)
+        auto realign = [&](int g) {
             const int p = P[g];
-            int top = TOP[g].x;
+            const int top = TOP[g].x;
             if (p > top) {
                 const int d = p - top;
                 const size_t ls = (size_t)(G + 1) * R;  // words per level
@@ -336,9 +354,13 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
                     for (int l = L - 1; l >= 0; --l) w[l * ls] = (l - d >= 0) ? w[(l - d) * ls] : 0;
                 }
                 TOP[g] = make_int2(p, (int)extractor_hi_of((AT*)0, p));
-                top = p;
+                m = max(m, p);
             }
-            m = max(m, top);
+        };
+        if (nr <= RAISED_MAX) {
+            for (int k = tid; k < nr; k += BLOCK) realign(sh.raised[k]);
+        } else {
+            for (int g = tid; g < G; g += BLOCK) realign(g);
         }
         if (!EPOCH) {
             // many groups whose tops rise at different times: no shared top
@@ -351,7 +373,7 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
         __syncthreads();
         const int nm = sh.newmax;
         int c = 0;
-        for (int g = tid; g < G; g += AGG_BLOCK) c += (TOP[g].x == nm);
+        for (int g = tid; g < G; g += BLOCK) c += (TOP[g].x == nm);
         if (c) atomicAdd(&sh.cnt, c);
         __syncthreads();
         uni = (sh.cnt == G);
@@ -364,9 +386,9 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
 
     uint32_t off[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) off[u] = (uint32_t)((u * AGG_BLOCK + tid) * VEC);
+    for (int u = 0; u < U; ++u) off[u] = (uint32_t)((u * BLOCK + tid) * VEC);
 
-    // software pipeline: tiles base+AGG_TILE .. base+PREFETCH*AGG_TILE are in
+    // software pipeline: tiles base+TILE .. base+PREFETCH*TILE are in
     // flight (in registers) while tile `base` is processed
     KT kb[PREFETCH + 1][ROWS_PER_THREAD];
     VT vb[PREFETCH + 1][ROWS_PER_THREAD];
@@ -375,13 +397,13 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
     for (int q = 0; q <= PREFETCH; ++q) inr[q] = 0;
 #pragma unroll
     for (int q = 0; q < PREFETCH; ++q)
-        if (c0 + (int64_t)q * AGG_TILE < c1)
-            inr[q] = load_tile<KT, VT, VEC, AGG_BLOCK>(keys, vals, c0 + (int64_t)q * AGG_TILE, c1, kb[q], vb[q], off);
+        if (c0 + (int64_t)q * TILE < c1)
+            inr[q] = load_tile<KT, VT, VEC, BLOCK>(keys, vals, c0 + (int64_t)q * TILE, c1, kb[q], vb[q], off);
 
-    for (int64_t base = c0; base < c1; base += AGG_TILE) {
-        const int64_t nb = base + (int64_t)PREFETCH * AGG_TILE;
+    for (int64_t base = c0; base < c1; base += TILE) {
+        const int64_t nb = base + (int64_t)PREFETCH * TILE;
         if (nb < c1)
-            inr[PREFETCH] = load_tile<KT, VT, VEC, AGG_BLOCK>(keys, vals, nb, c1, kb[PREFETCH], vb[PREFETCH], off);
+            inr[PREFETCH] = load_tile<KT, VT, VEC, BLOCK>(keys, vals, nb, c1, kb[PREFETCH], vb[PREFETCH], off);
         else
             inr[PREFETCH] = 0;
         const KT* kc = kb[0];
@@ -391,12 +413,12 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
         // classify: group (trash slot G for skipped rows) and required top
         int gi[ROWS_PER_THREAD], ji[ROWS_PER_THREAD];
         bool clean = true;  // no row of this lane is an error row
-        if (base + AGG_TILE <= c1)
+        if (base + TILE <= c1)
             classify_rows<true, SLICE, KT, VT, AT>(kc, vc, inr_c, G, gi, ji, clean, glo, Gfull);
         else
             classify_rows<false, SLICE, KT, VT, AT>(kc, vc, inr_c, G, gi, ji, clean, glo, Gfull);
         if (!clean)
-            err |= error_bits<KT, VT, AT>(kc, vc, base + AGG_TILE <= c1 ? (1u << ROWS_PER_THREAD) - 1 : inr_c, SLICE ? Gfull : G);
+            err |= error_bits<KT, VT, AT>(kc, vc, base + TILE <= c1 ? (1u << ROWS_PER_THREAD) - 1 : inr_c, SLICE ? Gfull : G);
 
         // tops of the rows' groups
         int ai[ROWS_PER_THREAD];
@@ -427,7 +449,7 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
                 sh.flag[sync % 3] = 1;
 #pragma unroll
                 for (int i = 0; i < ROWS_PER_THREAD; ++i)
-                    if (ji[i] > ai[i]) atomicMax(&P[gi[i]], ji[i]);
+                    if (ji[i] > ai[i]) raise_top(P, gi[i], ji[i], ai[i], sh, sync % 3);
             }
             if (!EPOCH) {
                 // look ahead: raise the tops of the prefetched tile's rows in
@@ -438,11 +460,13 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
                                                         glo, Gfull);
                 bool rn = false;
 #pragma unroll
-                for (int i = 0; i < ROWS_PER_THREAD; ++i)
-                    if (jn[i] > TOP[gn[i]].x) {
-                        atomicMax(&P[gn[i]], jn[i]);
+                for (int i = 0; i < ROWS_PER_THREAD; ++i) {
+                    const int cur = TOP[gn[i]].x;
+                    if (jn[i] > cur) {
+                        raise_top(P, gn[i], jn[i], cur, sh, sync % 3);
                         rn = true;
                     }
+                }
                 if (rn) sh.flag[sync % 3] = 1;
                 ahead = true;
             }
@@ -465,7 +489,7 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
 #pragma unroll
             for (int i = 0; i < ROWS_PER_THREAD; ++i) {
                 if (ji[i] > ai[i]) {
-                    atomicMax(&P[gi[i]], ji[i]);
+                    raise_top(P, gi[i], ji[i], ai[i], sh, sync % 3);
                     spill_row<AT, L>(spill, gi[i], (AT)vc[i], ji[i]);
                     gi[i] = G;  // nothing more for the bins
                     ++ns;
@@ -474,21 +498,24 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
             sh.flag[sync % 3] = 1;
             atomicAdd(&sh.spills[sync % 3], ns);
         }
-        // extract and deposit (skipped rows go to the trash slot)
+        // extract and deposit; skipped rows (trash slot G: errors, zeros, and
+        // in slice mode the rows of other slices) issue no LDS atomics
 #pragma unroll
         for (int i = 0; i < ROWS_PER_THREAD; ++i) {
             long long k[L];
             extract_from_hi<L>((AT)vc[i], hi_[i], k);
             unsigned char* w = smem + __umul24((uint32_t)gi[i], gstride) + lane_off;
+            if (gi[i] != G) {
 #pragma unroll
-            for (int l = 0; l < L; ++l)
-                atomicAdd(reinterpret_cast<unsigned long long*>(w + l * lstride), (unsigned long long)k[l]);
+                for (int l = 0; l < L; ++l)
+                    atomicAdd(reinterpret_cast<unsigned long long*>(w + l * lstride), (unsigned long long)k[l]);
+            }
         }
         if (epoch_left > 0 && --epoch_left == 0) {
             int sp;
             synchronise(sp);
             // many spills: the tops are still moving, go back to per-tile mode
-            epoch_left = (sp > AGG_TILE / 16) ? 0 : EPOCH_TILES;
+            epoch_left = (sp > TILE / 16) ? 0 : EPOCH_TILES;
             quiet = 0;
         }
 #pragma unroll

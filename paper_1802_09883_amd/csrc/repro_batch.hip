@@ -33,7 +33,8 @@ namespace {
 
 constexpr int64_t BATCH_DEFAULT_CHUNK = 128 * 1024;
 constexpr int BATCH_MAX_CHUNKS = 1024;   // per job; chunks grow to stay below
-constexpr int BATCH_MAX_WG = 256;        // persistent workgroups: one per CU
+constexpr int BATCH_BLOCK = 512;         // 8 waves: room for 256 VGPRs per lane, no spills
+constexpr int BATCH_MAX_WG = 512;        // persistent workgroups: as many as fit (one or two per CU)
 
 // Device record of a job (built by the planner).
 struct BatchJob {
@@ -43,37 +44,43 @@ struct BatchJob {
     void* out;
     long long n;
     long long chunk;      // rows per chunk (multiple of the tile)
-    long long part_off;   // byte offset of this job's partials in the workspace
+    long long part_off;   // byte offset of this job's partials in the partial area
+    long long spill_off;  // byte offset of its spill array in the spill area (epoch mode), or -1
     int G, L, accumulate, vec;
     int nslices, gs, R;   // slices, groups per slice (the last may be smaller), LDS replicas
     int nchunks;
     int done_off;         // first completion counter of this job (one per slice)
-    int pad[3];
+    int pad[1];
 };
 
 struct BatchItem {
     int job, chunk, slice, pad;
 };
 
-// Workspace: [head][jobs][items][counters][partials], offsets in the head.
+// Workspace: [head][jobs][items][counters | spill arrays][partials]; the
+// counters and spill words (zeroed by k_batch_reset) are one contiguous
+// range.  Offsets are in the head.
 struct BatchHead {
     int next;  // queue position (reset by k_batch_reset)
     int nitems;
     int njobs;
     int ncounters;
-    long long off_jobs, off_items, off_counters, off_partials;
+    long long off_jobs, off_items, off_counters, off_spill, off_partials;
+    long long zero_words;  // 8-byte words from off_counters that k_batch_reset clears
 };
 
 struct BatchLayout {
-    size_t jobs, items, counters, partials, total;
+    size_t jobs, items, counters, spill, partials, total;
 };
 
-inline BatchLayout batch_layout(int njobs, int64_t nitems, int64_t ncounters, size_t partial_bytes) {
+inline BatchLayout batch_layout(int njobs, int64_t nitems, int64_t ncounters, size_t spill_bytes,
+                                size_t partial_bytes) {
     BatchLayout b;
     b.jobs = 256;
     b.items = b.jobs + align_up((size_t)njobs * sizeof(BatchJob), 256);
     b.counters = b.items + align_up((size_t)nitems * sizeof(BatchItem), 256);
-    b.partials = b.counters + align_up((size_t)ncounters * 4, 256);
+    b.spill = b.counters + align_up((size_t)ncounters * 4, 256);
+    b.partials = b.spill + align_up(spill_bytes, 256);
     b.total = b.partials + align_up(partial_bytes, 256);
     return b;
 }
@@ -131,6 +138,20 @@ __device__ __forceinline__ void add_levels(const long long* x, int top, int J, l
     }
 }
 
+// Adds the spill words of one group (exact 128-bit units H * 2^64 + w per
+// absolute lattice index) kept at levels J - l, l < L, to (hi, lo).
+template <class AT, int L>
+__device__ __forceinline__ void add_spill(const unsigned long long* sw, int J, long long* hi, long long* lo) {
+    constexpr int c = Fmt<AT>::CARRY;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const unsigned long long* w = sw + (size_t)(J - l) * 2;
+        const i128 T = (i128)(long long)w[1] * ((i128)1 << 64) + (i128)w[0];
+        hi[l] += (long long)(T >> c);
+        lo[l] += (long long)(T & ((1ll << c) - 1));
+    }
+}
+
 // Starts (hi, lo) level words at top J from the caller's state of group g
 // (C into hi, the low part of S into lo, moved down by J - top), or from
 // the empty state when the job overwrites.  Returns nothing: J must already
@@ -158,17 +179,20 @@ __device__ __forceinline__ int state_top_of(const AT* S, int g, bool use, int L)
 
 // One item: aggregate, then fold or publish a partial; the last item of a
 // slice folds the slice.  Returns the lane's status bits.
-template <class KT, class VT, class AT, int L, int VEC>
+template <class KT, class VT, class AT, int L, int VEC, bool EPOCH>
 __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned char* partials, int* counters,
-                             unsigned char* smem, AggShared& sh, int* s_last) {
+                             unsigned long long* spill_area, unsigned char* smem, AggShared& sh, int* s_last) {
+    constexpr int NJ = Fmt<AT>::JMAX + 1;
     const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)bi.chunk * jb.chunk;
     const int64_t r1 = min((int64_t)jb.n, r0 + jb.chunk);
     const int64_t glo = (int64_t)bi.slice * jb.gs;
     const int Gs = (int)min((int64_t)jb.gs, (int64_t)jb.G - glo);
     const int R = jb.R;
-    const uint32_t err = aggregate_range<KT, VT, AT, L, VEC, false, true>(
-        static_cast<const KT*>(jb.keys), static_cast<const VT*>(jb.vals), r0, r1, Gs, R, smem, sh, nullptr, glo,
+    // epoch mode (unsliced jobs): rows above a frozen top go to the job's spill array
+    unsigned long long* spill = EPOCH ? spill_area + jb.spill_off / 8 : nullptr;
+    const uint32_t err = aggregate_range<KT, VT, AT, L, VEC, EPOCH, true, BATCH_BLOCK>(
+        static_cast<const KT*>(jb.keys), static_cast<const VT*>(jb.vals), r0, r1, Gs, R, smem, sh, spill, glo,
         jb.G);
     const long long* bins = reinterpret_cast<const long long*>(smem);
     const int2* TOP = reinterpret_cast<const int2*>(bins + (size_t)(Gs + 1) * R * L);
@@ -184,13 +208,15 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
         }
     };
     if (jb.nchunks == 1) {
-        for (int g = tid; g < Gs; g += AGG_BLOCK) {
+        if (EPOCH) __threadfence();  // this workgroup's spill atomics, read back below
+        for (int g = tid; g < Gs; g += BATCH_BLOCK) {
             const int gg = (int)glo + g;
             long long x[L], hi[L], lo[L];
             level_sums(g, x);
             const int J = max(TOP[g].x, state_top_of(S, gg, jb.accumulate, L));
             start_from_state<AT, L>(S, C, jb.G, gg, jb.accumulate, J, hi, lo);
             add_levels<AT, L>(x, TOP[g].x, J, hi, lo);
+            if (EPOCH) add_spill<AT, L>(spill + (size_t)g * NJ * 2, J, hi, lo);
             write_group<AT, L>(hi, lo, J, S, C, jb.G, gg, out);
         }
         __syncthreads();  // LDS is reused by the next item
@@ -203,7 +229,7 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
         unsigned char* pp = part0 + (size_t)bi.chunk * pbytes;
         int* ptop = reinterpret_cast<int*>(pp);
         long long* pK = reinterpret_cast<long long*>(pp + align_up((size_t)jb.gs * 4, 8));
-        for (int g = tid; g < Gs; g += AGG_BLOCK) {
+        for (int g = tid; g < Gs; g += BATCH_BLOCK) {
             long long x[L];
             level_sums(g, x);
             ptop[g] = TOP[g].x;
@@ -217,7 +243,7 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
     __syncthreads();
     if (*s_last) {
         __threadfence();  // see the other items' partials
-        for (int g = tid; g < Gs; g += AGG_BLOCK) {
+        for (int g = tid; g < Gs; g += BATCH_BLOCK) {
             const int gg = (int)glo + g;
             long long hi[L], lo[L];
             int J = state_top_of(S, gg, jb.accumulate, L);
@@ -232,6 +258,7 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
                 for (int l = 0; l < L; ++l) x[l] = pK[(size_t)l * jb.gs + g];
                 add_levels<AT, L>(x, reinterpret_cast<const int*>(pp)[g], J, hi, lo);
             }
+            if (EPOCH) add_spill<AT, L>(spill + (size_t)g * NJ * 2, J, hi, lo);
             write_group<AT, L>(hi, lo, J, S, C, jb.G, gg, out);
         }
     }
@@ -241,19 +268,24 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
 
 template <class KT, class VT, class AT, int L>
 __device__ __forceinline__ uint32_t run_item_vec(const BatchJob& jb, const BatchItem& bi, unsigned char* partials,
-                                                 int* counters, unsigned char* smem, AggShared& sh, int* s_last) {
+                                                 int* counters, unsigned long long* spill, unsigned char* smem,
+                                                 AggShared& sh, int* s_last) {
     constexpr int VEC = 16 / sizeof(VT);
-    if (jb.vec) return run_item<KT, VT, AT, L, VEC>(jb, bi, partials, counters, smem, sh, s_last);
-    return run_item<KT, VT, AT, L, 1>(jb, bi, partials, counters, smem, sh, s_last);
+    if (jb.spill_off >= 0) {
+        if (jb.vec) return run_item<KT, VT, AT, L, VEC, true>(jb, bi, partials, counters, spill, smem, sh, s_last);
+        return run_item<KT, VT, AT, L, 1, true>(jb, bi, partials, counters, spill, smem, sh, s_last);
+    }
+    if (jb.vec) return run_item<KT, VT, AT, L, VEC, false>(jb, bi, partials, counters, spill, smem, sh, s_last);
+    return run_item<KT, VT, AT, L, 1, false>(jb, bi, partials, counters, spill, smem, sh, s_last);
 }
 
 // Zeroes the queue position and the completion counters (a kernel, so that
 // the launch can be captured into a graph without memset nodes).
 __global__ void __launch_bounds__(256) k_batch_reset(unsigned char* __restrict__ ws) {
     BatchHead* hd = reinterpret_cast<BatchHead*>(ws);
-    int* counters = reinterpret_cast<int*>(ws + hd->off_counters);
-    const int nc = hd->ncounters;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < nc; i += gridDim.x * 256) counters[i] = 0;
+    unsigned long long* z = reinterpret_cast<unsigned long long*>(ws + hd->off_counters);
+    const long long nz = hd->zero_words;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < nz; i += (long long)gridDim.x * 256) z[i] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) hd->next = 0;
 }
 
@@ -261,7 +293,7 @@ __global__ void __launch_bounds__(256) k_batch_reset(unsigned char* __restrict__
 // empty (each loop iteration advances the shared position by one, so every
 // workgroup reaches the exit).
 template <class KT, class VT, class AT>
-__global__ void __launch_bounds__(AGG_BLOCK) k_batch(unsigned char* __restrict__ ws, uint32_t* __restrict__ status) {
+__global__ void __launch_bounds__(BATCH_BLOCK) k_batch(unsigned char* __restrict__ ws, uint32_t* __restrict__ status) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ AggShared sh;
     __shared__ int s_item, s_last;
@@ -269,6 +301,7 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_batch(unsigned char* __restrict__
     const BatchJob* jobs = reinterpret_cast<const BatchJob*>(ws + hd->off_jobs);
     const BatchItem* items = reinterpret_cast<const BatchItem*>(ws + hd->off_items);
     int* counters = reinterpret_cast<int*>(ws + hd->off_counters);
+    unsigned long long* spill = reinterpret_cast<unsigned long long*>(ws + hd->off_spill);
     unsigned char* partials = ws + hd->off_partials;
     const int nitems = hd->nitems;
     uint32_t err = 0;
@@ -281,10 +314,10 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_batch(unsigned char* __restrict__
         const BatchItem bi = items[it];
         const BatchJob jb = jobs[bi.job];
         switch (jb.L) {
-            case 1: err |= run_item_vec<KT, VT, AT, 1>(jb, bi, partials, counters, smem, sh, &s_last); break;
-            case 2: err |= run_item_vec<KT, VT, AT, 2>(jb, bi, partials, counters, smem, sh, &s_last); break;
-            case 3: err |= run_item_vec<KT, VT, AT, 3>(jb, bi, partials, counters, smem, sh, &s_last); break;
-            default: err |= run_item_vec<KT, VT, AT, 4>(jb, bi, partials, counters, smem, sh, &s_last); break;
+            case 1: err |= run_item_vec<KT, VT, AT, 1>(jb, bi, partials, counters, spill, smem, sh, &s_last); break;
+            case 2: err |= run_item_vec<KT, VT, AT, 2>(jb, bi, partials, counters, spill, smem, sh, &s_last); break;
+            case 3: err |= run_item_vec<KT, VT, AT, 3>(jb, bi, partials, counters, spill, smem, sh, &s_last); break;
+            default: err |= run_item_vec<KT, VT, AT, 4>(jb, bi, partials, counters, spill, smem, sh, &s_last); break;
         }
     }
     report(status, err);
@@ -298,6 +331,7 @@ struct HostPlan {
     std::vector<BatchJob> jobs;
     std::vector<BatchItem> items;
     int64_t ncounters = 0;
+    size_t spill_bytes = 0;
     size_t partial_bytes = 0;
     size_t lds = 0;
     BatchLayout lay{};
@@ -330,7 +364,9 @@ bool make_batch_plan(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
     hp->jobs.resize(njobs);
     hp->items.clear();
     hp->ncounters = 0;
+    hp->spill_bytes = 0;
     hp->partial_bytes = 0;
+    const int NJ = (T == REPRO_F64 ? 51 : 14) + 1;  // lattice indices of the accumulator format
     hp->lds = 0;
     std::vector<int64_t> cost;
     for (int j = 0; j < njobs; ++j) {
@@ -364,6 +400,13 @@ bool make_batch_plan(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
         // a job without rows still gets one item per slice: it writes the
         // (empty, or unchanged) states and the finalised sums
         b.nchunks = u.n > 0 ? (int)((u.n + chunk - 1) / chunk) : 1;
+        // epoch mode for jobs in one slice whose items span several tiles: a
+        // spill array of NJ exact 128-bit words per group
+        b.spill_off = -1;
+        if (b.nslices == 1 && std::min<int64_t>(u.n, chunk) >= 4 * (int64_t)AGG_TILE) {
+            b.spill_off = (long long)hp->spill_bytes;
+            hp->spill_bytes += (size_t)b.gs * NJ * 16;
+        }
         if (b.nchunks > 1) {
             b.done_off = (int)hp->ncounters;
             hp->ncounters += b.nslices;
@@ -386,7 +429,7 @@ bool make_batch_plan(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
         for (size_t i = 0; i < idx.size(); ++i) sorted[i] = hp->items[idx[i]];
         hp->items.swap(sorted);
     }
-    hp->lay = batch_layout(njobs, (int64_t)hp->items.size(), hp->ncounters, hp->partial_bytes);
+    hp->lay = batch_layout(njobs, (int64_t)hp->items.size(), hp->ncounters, hp->spill_bytes, hp->partial_bytes);
     return true;
 }
 
@@ -406,12 +449,12 @@ const void* pick_kernel(int kt, int vt, int T) {
 
 int launch_plan(const repro_batch_plan* p, uint32_t* status, hipStream_t st) {
     unsigned char* ws = static_cast<unsigned char*>(p->workspace);
-    hipLaunchKernelGGL(k_batch_reset, dim3(64), dim3(256), 0, st, ws);
+    hipLaunchKernelGGL(k_batch_reset, dim3(1024), dim3(256), 0, st, ws);
     if (hipGetLastError() != hipSuccess) return REPRO_EHIP;
     if (p->items == 0) return REPRO_OK;
     const void* fn = pick_kernel(p->kt, p->vt, p->T);  // its LDS limit was raised by the prepare call
     void* args[] = {&ws, &status};
-    if (hipLaunchKernel(fn, dim3(p->grid), dim3(AGG_BLOCK), args, (size_t)p->lds_bytes, st) != hipSuccess)
+    if (hipLaunchKernel(fn, dim3(p->grid), dim3(BATCH_BLOCK), args, (size_t)p->lds_bytes, st) != hipSuccess)
         return REPRO_EHIP;
     return REPRO_OK;
 }
@@ -444,7 +487,9 @@ int repro_batch_prepare(const repro_batch_job* jobs, int njobs, repro_key_t kt, 
     hd.off_jobs = (long long)hp.lay.jobs;
     hd.off_items = (long long)hp.lay.items;
     hd.off_counters = (long long)hp.lay.counters;
+    hd.off_spill = (long long)hp.lay.spill;
     hd.off_partials = (long long)hp.lay.partials;
+    hd.zero_words = (long long)((hp.lay.partials - hp.lay.counters) / 8);
     memcpy(img.data(), &hd, sizeof(hd));
     if (njobs) memcpy(img.data() + hp.lay.jobs, hp.jobs.data(), hp.jobs.size() * sizeof(BatchJob));
     if (!hp.items.empty()) memcpy(img.data() + hp.lay.items, hp.items.data(), hp.items.size() * sizeof(BatchItem));
