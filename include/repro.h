@@ -217,6 +217,72 @@ int repro_batch_tune(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
                      hipStream_t stream);
 
 /*
+ * ------------------------------------------------------------ serving
+ *
+ * A request loop for GroupBy queries with several reproducible SUM
+ * aggregates (RSum(expression, L), Sec. V-D; the expression is a column or
+ * the IEEE product of two columns, rounded once, no fused multiply-add).
+ * Queries are admitted in arrival order when a slot and device memory are
+ * free; an admitted query's states live in the server's arena and take its
+ * rows chunk by chunk (the resumable state of Alg. 2: each chunk is added to
+ * the resident states), then are finalised into the caller's outputs.
+ * Admitted queries run on separate streams, so their work overlaps on the
+ * device.  Every result is bit-identical to repro_groupby_sum of the same
+ * expression column alone: admission order, concurrency and chunking do
+ * not change a bit.
+ */
+#define REPRO_MAX_COLS 8
+#define REPRO_MAX_AGGS 4
+
+typedef struct {
+    const int32_t* keys;                 /* device, n entries, dense ids           */
+    const double* cols[REPRO_MAX_COLS];  /* device f64 columns, n entries (or NULL) */
+    int64_t n;                           /* rows, >= 0                              */
+    int64_t num_groups;                  /* 1 .. 2^31-1                             */
+    int L;                               /* levels of every aggregate, 1..4         */
+    int naggs;                           /* 1 .. REPRO_MAX_AGGS                     */
+    int agg_a[REPRO_MAX_AGGS];           /* SUM(cols[agg_a]) ...                    */
+    int agg_b[REPRO_MAX_AGGS];           /* ... * cols[agg_b] when agg_b >= 0       */
+    double* out[REPRO_MAX_AGGS];         /* device f64[num_groups] finalised sums   */
+    uint32_t* status;                    /* device status word (OR-ed), or NULL     */
+} repro_query;
+
+typedef struct {
+    int slots;           /* queries on the GPU at once (one stream each), 1..64 */
+    int64_t chunk_rows;  /* rows added to a query's states per call (0: 16M)   */
+} repro_server_config;
+
+typedef struct repro_server repro_server;
+
+/* Arena bytes a query needs while admitted (0 for an invalid query). */
+size_t repro_query_bytes(const repro_query* q, const repro_server_config* cfg);
+
+/* A server over a caller-owned device arena (256-byte aligned), which it
+ * sub-allocates for admitted queries.  Creates its streams (default
+ * priority). */
+int repro_server_create(void* arena, size_t arena_bytes, const repro_server_config* cfg, repro_server** srv);
+
+/* Queues a query (host record copied; device buffers must stay valid until
+ * the query completes).  *ticket numbers queries from 0 in submission order.
+ * REPRO_EINVAL for an invalid query or one larger than the whole arena. */
+int repro_server_submit(repro_server* srv, const repro_query* q, int64_t* ticket);
+
+/* Makes progress without blocking: retires finished queries (freeing their
+ * memory and slot), then admits queued queries in order while they fit.
+ * Writes up to `cap` completed tickets and their completion times (seconds
+ * on the host's monotonic clock) and the counts of completed (in this call),
+ * queued and running queries. */
+int repro_server_poll(repro_server* srv, int64_t* tickets, double* times, int cap, int* ndone, int* nqueued,
+                      int* nrunning);
+
+/* The host's monotonic clock (seconds) used for completion times. */
+double repro_server_clock(void);
+
+/* Waits for the running queries, then destroys the server (queued queries
+ * are dropped). */
+int repro_server_destroy(repro_server* srv);
+
+/*
  * Profiling aid.  repro_profile_arm(k) makes the next k repro_groupby_sum
  * calls issued by the calling host thread record a pair of HIP events on
  * their stream, right before and right after the aggregation kernel (the

@@ -33,6 +33,22 @@ class BatchConfig(ctypes.Structure):
     _fields_ = [("chunk_rows", ctypes.c_int64), ("max_slice_groups", ctypes.c_int), ("order", ctypes.c_int)]
 
 
+MAX_COLS, MAX_AGGS = 8, 4
+
+
+class Query(ctypes.Structure):
+    """repro_query of include/repro.h."""
+    _fields_ = [("keys", ctypes.c_void_p), ("cols", ctypes.c_void_p * MAX_COLS), ("n", ctypes.c_int64),
+                ("num_groups", ctypes.c_int64), ("L", ctypes.c_int), ("naggs", ctypes.c_int),
+                ("agg_a", ctypes.c_int * MAX_AGGS), ("agg_b", ctypes.c_int * MAX_AGGS),
+                ("out", ctypes.c_void_p * MAX_AGGS), ("status", ctypes.c_void_p)]
+
+
+class ServerConfig(ctypes.Structure):
+    """repro_server_config of include/repro.h."""
+    _fields_ = [("slots", ctypes.c_int), ("chunk_rows", ctypes.c_int64)]
+
+
 class BatchPlan(ctypes.Structure):
     """repro_batch_plan of include/repro.h."""
     _fields_ = [("workspace", ctypes.c_void_p), ("items", ctypes.c_int64), ("grid", ctypes.c_int),
@@ -77,6 +93,20 @@ def load():
     lib.repro_batch_launch.argtypes = [bp, vp, vp]
     lib.repro_batch_tune.restype = ctypes.c_int
     lib.repro_batch_tune.argtypes = [bj, i32, i32, i32, i32, vp, sz, bc, ctypes.POINTER(ctypes.c_float), vp]
+    qp, scp = ctypes.POINTER(Query), ctypes.POINTER(ServerConfig)
+    lib.repro_query_bytes.restype = sz
+    lib.repro_query_bytes.argtypes = [qp, scp]
+    lib.repro_server_create.restype = ctypes.c_int
+    lib.repro_server_create.argtypes = [vp, sz, scp, ctypes.POINTER(vp)]
+    lib.repro_server_submit.restype = ctypes.c_int
+    lib.repro_server_submit.argtypes = [vp, qp, ctypes.POINTER(i64)]
+    lib.repro_server_poll.restype = ctypes.c_int
+    lib.repro_server_poll.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double), i32,
+                                      ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.repro_server_clock.restype = ctypes.c_double
+    lib.repro_server_clock.argtypes = []
+    lib.repro_server_destroy.restype = ctypes.c_int
+    lib.repro_server_destroy.argtypes = [vp]
     lib.repro_version.restype = ctypes.c_char_p
     lib.repro_version.argtypes = []
     for name in ("repro_state_init", "repro_groupby_sum", "repro_merge", "repro_finalize",

@@ -254,3 +254,77 @@ def batch_tune(jobs, T=torch.float64, stream=None):
     _lib.check(lib.repro_batch_tune(arr, len(jobs), kt, vt, _T(T), _vp(ws), need, ctypes.byref(best),
                                     ctypes.byref(ms), ctypes.c_void_p(s.cuda_stream)), "batch_tune")
     return {"chunk_rows": best.chunk_rows, "max_slice_groups": best.max_slice_groups, "order": best.order}, ms.value
+
+
+# ----------------------------------------------------------------- serving
+
+class QuerySpec:
+    """A GroupBy query with up to four SUM aggregates: each aggregate is
+    SUM(cols[a]) or SUM(cols[a] * cols[b]).  ``keys`` int32 and ``cols``
+    float64 device tensors of equal length; ``out`` receives one float64
+    tensor of num_groups finalised sums per aggregate."""
+
+    def __init__(self, keys, cols, num_groups, aggs, L=2, status=None):
+        self.keys, self.cols, self.num_groups, self.aggs, self.L = keys, list(cols), int(num_groups), list(aggs), L
+        self.status = status
+        self.out = [torch.empty(self.num_groups, dtype=torch.float64, device=keys.device) for _ in self.aggs]
+
+    def record(self):
+        q = _lib.Query()
+        q.keys = _vp(self.keys).value
+        for i, c in enumerate(self.cols[:_lib.MAX_COLS]):
+            q.cols[i] = _vp(c).value
+        q.n = self.keys.numel()
+        q.num_groups = self.num_groups
+        q.L = self.L
+        q.naggs = len(self.aggs)  # more than MAX_AGGS is rejected by the library
+        for i, (a, b) in enumerate(self.aggs[:_lib.MAX_AGGS]):
+            q.agg_a[i], q.agg_b[i] = a, (-1 if b is None else b)
+            q.out[i] = _vp(self.out[i]).value
+        q.status = _vp(self.status).value if self.status is not None else None
+        return q
+
+
+class Server:
+    """Request loop over a device arena (see include/repro.h): submit()
+    queues a query, poll() retires finished queries and admits queued ones
+    without blocking."""
+
+    def __init__(self, arena_bytes, slots=4, chunk_rows=0, device="cuda"):
+        self.lib = _lib.load()
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=device)
+        self.cfg = _lib.ServerConfig(slots, chunk_rows)
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.repro_server_create(_vp(self.arena), arena_bytes, ctypes.byref(self.cfg),
+                                                ctypes.byref(h)), "server_create")
+        self.h = h
+        self.live = {}  # ticket -> query (keeps its tensors alive)
+
+    def query_bytes(self, spec):
+        return int(self.lib.repro_query_bytes(ctypes.byref(spec.record()), ctypes.byref(self.cfg)))
+
+    def submit(self, spec):
+        t = ctypes.c_int64()
+        _lib.check(self.lib.repro_server_submit(self.h, ctypes.byref(spec.record()), ctypes.byref(t)), "submit")
+        self.live[t.value] = spec
+        return t.value
+
+    def poll(self, cap=256):
+        """Returns ([(ticket, completion time)], queued, running)."""
+        tk = (ctypes.c_int64 * cap)()
+        tm = (ctypes.c_double * cap)()
+        nd, nq, nr = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _lib.check(self.lib.repro_server_poll(self.h, tk, tm, cap, ctypes.byref(nd), ctypes.byref(nq),
+                                              ctypes.byref(nr)), "poll")
+        done = [(tk[i], tm[i]) for i in range(min(nd.value, cap))]
+        for t, _ in done:
+            self.live.pop(t, None)
+        return done, nq.value, nr.value
+
+    def clock(self):
+        return self.lib.repro_server_clock()
+
+    def close(self):
+        if self.h:
+            _lib.check(self.lib.repro_server_destroy(self.h), "server_destroy")
+            self.h = None

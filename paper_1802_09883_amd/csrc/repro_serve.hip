@@ -1,0 +1,305 @@
+// repro_serve.hip -- request loop for reproducible GroupBy-SUM queries
+// (librepro, gfx950).
+//
+// Paper: Mueller, Arteaga, Hoefler, Alonso, "Reproducible Floating-Point
+// Aggregation in RDBMSs" (arXiv 1802.09883).  A query is a GroupBy with
+// several RSum(expression, L) aggregates (Sec. V-D); its states are resumable
+// (Alg. 2 loads and stores them), so they stay resident in device memory and
+// take the query's rows chunk by chunk; exact level sums make the result
+// independent of the chunking and of whatever else runs on the device.
+//
+// Host side: a FIFO of submitted queries, a fixed set of slots (one stream
+// each) and a first-fit allocator over a caller-owned device arena.  A query
+// is admitted when a slot is free and its memory fits; its whole pipeline is
+// then enqueued on its slot's stream (state initialisation, product columns,
+// one repro_groupby_sum per chunk and aggregate, finalisation, an event).
+// Polling retires queries whose event completed and admits the next ones.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <deque>
+#include <iterator>
+#include <map>
+#include <vector>
+
+#include "repro.h"
+
+namespace {
+
+constexpr int64_t SERVE_DEFAULT_CHUNK = 16ll << 20;
+constexpr size_t SERVE_ALIGN = 256;
+
+inline size_t up(size_t x) { return (x + SERVE_ALIGN - 1) / SERVE_ALIGN * SERVE_ALIGN; }
+
+// out[i] = a[i] * b[i], one IEEE rounding (the build disables contraction).
+__global__ void __launch_bounds__(256) k_mul(const double* __restrict__ a, const double* __restrict__ b,
+                                             double* __restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        out[i] = a[i] * b[i];
+}
+
+// First-fit allocator over [0, size) with coalescing; offsets 256-aligned.
+class Arena {
+   public:
+    void init(size_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+    }
+    bool alloc(size_t bytes, size_t* off) {
+        bytes = up(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = up(bytes);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+   private:
+    std::map<size_t, size_t> free_;
+};
+
+// Arena layout of one admitted query.
+struct QueryLayout {
+    size_t state_bytes, ws_bytes, total;
+    size_t off_state[REPRO_MAX_AGGS], off_prod[REPRO_MAX_AGGS], off_ws;
+    int64_t chunk;
+};
+
+bool valid_query(const repro_query* q) {
+    if (!q || q->n < 0 || q->num_groups < 1 || q->num_groups > INT32_MAX || q->L < 1 || q->L > 4 || q->naggs < 1 ||
+        q->naggs > REPRO_MAX_AGGS)
+        return false;
+    if (q->n > 0 && !q->keys) return false;
+    for (int a = 0; a < q->naggs; ++a) {
+        const int ca = q->agg_a[a], cb = q->agg_b[a];
+        if (ca < 0 || ca >= REPRO_MAX_COLS || cb >= REPRO_MAX_COLS || !q->out[a]) return false;
+        if (q->n > 0 && (!q->cols[ca] || (cb >= 0 && !q->cols[cb]))) return false;
+    }
+    return true;
+}
+
+bool layout_query(const repro_query* q, int64_t chunk_cfg, QueryLayout* ly) {
+    if (!valid_query(q)) return false;
+    memset(ly, 0, sizeof(*ly));
+    ly->chunk = chunk_cfg > 0 ? chunk_cfg : SERVE_DEFAULT_CHUNK;
+    ly->state_bytes = repro_state_bytes(q->num_groups, REPRO_F64, q->L);
+    ly->ws_bytes = q->n > 0 ? repro_workspace_bytes(std::min<int64_t>(q->n, ly->chunk), q->num_groups, REPRO_I32,
+                                                    REPRO_F64, REPRO_F64, q->L)
+                            : 0;
+    if (ly->state_bytes == 0) return false;
+    size_t off = 0;
+    for (int a = 0; a < q->naggs; ++a) {
+        ly->off_state[a] = off;
+        off += up(ly->state_bytes);
+    }
+    for (int a = 0; a < q->naggs; ++a) {
+        ly->off_prod[a] = off;
+        if (q->agg_b[a] >= 0) off += up((size_t)q->n * 8);
+    }
+    ly->off_ws = off;
+    off += up(ly->ws_bytes);
+    ly->total = off;
+    return true;
+}
+
+struct Pending {
+    int64_t ticket;
+    repro_query q;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    int64_t ticket = -1;
+    size_t off = 0, bytes = 0;
+};
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct repro_server {
+    unsigned char* arena = nullptr;
+    size_t arena_bytes = 0;
+    int64_t chunk = SERVE_DEFAULT_CHUNK;
+    Arena alloc;
+    std::vector<Slot> slots;
+    std::deque<Pending> queue;
+    int64_t next_ticket = 0;
+};
+
+namespace {
+
+// Enqueues an admitted query's whole pipeline on its slot's stream.
+int enqueue_query(repro_server* s, Slot& sl, const repro_query& q, const QueryLayout& ly) {
+    hipStream_t st = sl.stream;
+    unsigned char* base = s->arena + sl.off;
+    const int64_t G = q.num_groups;
+    const double* vals[REPRO_MAX_AGGS];
+    for (int a = 0; a < q.naggs; ++a) {
+        if (repro_state_init(base + ly.off_state[a], G, REPRO_F64, q.L, st) != REPRO_OK) return REPRO_EHIP;
+        vals[a] = q.cols[q.agg_a[a]];
+        if (q.agg_b[a] >= 0 && q.n > 0) {
+            double* prod = reinterpret_cast<double*>(base + ly.off_prod[a]);
+            const int64_t blocks = std::min<int64_t>(4096, (q.n + 255) / 256);
+            hipLaunchKernelGGL(k_mul, dim3((unsigned)blocks), dim3(256), 0, st, q.cols[q.agg_a[a]], q.cols[q.agg_b[a]],
+                               prod, q.n);
+            if (hipGetLastError() != hipSuccess) return REPRO_EHIP;
+            vals[a] = prod;
+        }
+    }
+    for (int64_t r0 = 0; r0 < q.n; r0 += ly.chunk) {
+        const int64_t m = std::min<int64_t>(ly.chunk, q.n - r0);
+        for (int a = 0; a < q.naggs; ++a) {
+            const int rc = repro_groupby_sum(q.keys + r0, REPRO_I32, vals[a] + r0, REPRO_F64, m, G, REPRO_F64, q.L,
+                                             base + ly.off_state[a], base + ly.off_ws, ly.ws_bytes, q.status, st);
+            if (rc != REPRO_OK) return rc;
+        }
+    }
+    for (int a = 0; a < q.naggs; ++a)
+        if (repro_finalize(base + ly.off_state[a], G, REPRO_F64, q.L, q.out[a], st) != REPRO_OK) return REPRO_EHIP;
+    if (hipEventRecord(sl.done, st) != hipSuccess) return REPRO_EHIP;
+    return REPRO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t repro_query_bytes(const repro_query* q, const repro_server_config* cfg) {
+    QueryLayout ly;
+    if (!layout_query(q, cfg ? cfg->chunk_rows : 0, &ly)) return 0;
+    return ly.total;
+}
+
+double repro_server_clock(void) { return now_s(); }
+
+int repro_server_create(void* arena, size_t arena_bytes, const repro_server_config* cfg, repro_server** srv) {
+    if (!srv || !arena || (uintptr_t)arena % SERVE_ALIGN != 0 || arena_bytes < SERVE_ALIGN) return REPRO_EINVAL;
+    const int nslots = cfg ? cfg->slots : 4;
+    if (nslots < 1 || nslots > 64 || (cfg && cfg->chunk_rows < 0)) return REPRO_EINVAL;
+    repro_server* s = new repro_server();
+    s->arena = static_cast<unsigned char*>(arena);
+    s->arena_bytes = arena_bytes / SERVE_ALIGN * SERVE_ALIGN;
+    s->chunk = (cfg && cfg->chunk_rows > 0) ? cfg->chunk_rows : SERVE_DEFAULT_CHUNK;
+    s->alloc.init(s->arena_bytes);
+    s->slots.resize(nslots);
+    for (Slot& sl : s->slots) {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            repro_server_destroy(s);
+            return REPRO_EHIP;
+        }
+    }
+    *srv = s;
+    return REPRO_OK;
+}
+
+int repro_server_submit(repro_server* s, const repro_query* q, int64_t* ticket) {
+    if (!s) return REPRO_EINVAL;
+    QueryLayout ly;
+    if (!layout_query(q, s->chunk, &ly) || up(ly.total) > s->arena_bytes) return REPRO_EINVAL;
+    Pending p;
+    p.ticket = s->next_ticket++;
+    p.q = *q;
+    s->queue.push_back(p);
+    if (ticket) *ticket = p.ticket;
+    return REPRO_OK;
+}
+
+int repro_server_poll(repro_server* s, int64_t* tickets, double* times, int cap, int* ndone, int* nqueued,
+                      int* nrunning) {
+    if (!s) return REPRO_EINVAL;
+    int done = 0;
+    // retire
+    for (Slot& sl : s->slots) {
+        if (!sl.busy) continue;
+        const hipError_t e = hipEventQuery(sl.done);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) return REPRO_EHIP;
+        const double t = now_s();
+        if (done < cap) {
+            if (tickets) tickets[done] = sl.ticket;
+            if (times) times[done] = t;
+        }
+        ++done;
+        s->alloc.release(sl.off, sl.bytes);
+        sl.busy = false;
+        sl.ticket = -1;
+    }
+    // admit, in order, while a slot and memory are free
+    while (!s->queue.empty()) {
+        Slot* free_slot = nullptr;
+        for (Slot& sl : s->slots)
+            if (!sl.busy) {
+                free_slot = &sl;
+                break;
+            }
+        if (!free_slot) break;
+        const Pending& p = s->queue.front();
+        QueryLayout ly;
+        if (!layout_query(&p.q, s->chunk, &ly)) return REPRO_EINVAL;
+        size_t off = 0;
+        if (!s->alloc.alloc(ly.total, &off)) break;  // wait for memory
+        free_slot->busy = true;
+        free_slot->ticket = p.ticket;
+        free_slot->off = off;
+        free_slot->bytes = ly.total;
+        const repro_query q = p.q;
+        s->queue.pop_front();
+        const int rc = enqueue_query(s, *free_slot, q, ly);
+        if (rc != REPRO_OK) return rc;
+    }
+    if (ndone) *ndone = done;
+    if (nqueued) *nqueued = (int)s->queue.size();
+    if (nrunning) {
+        int r = 0;
+        for (const Slot& sl : s->slots) r += sl.busy;
+        *nrunning = r;
+    }
+    return REPRO_OK;
+}
+
+int repro_server_destroy(repro_server* s) {
+    if (!s) return REPRO_EINVAL;
+    int rc = REPRO_OK;
+    for (Slot& sl : s->slots) {
+        if (sl.stream) {
+            if (hipStreamSynchronize(sl.stream) != hipSuccess) rc = REPRO_EHIP;
+            (void)hipStreamDestroy(sl.stream);
+        }
+        if (sl.done) (void)hipEventDestroy(sl.done);
+    }
+    delete s;
+    return rc;
+}
+
+}  // extern "C"

@@ -96,3 +96,33 @@ def batched_job(rows: int, groups: int, job: int, salt: int = 0):
     keys = rk.integers(0, groups, rows, dtype=np.int32)
     vals = np.ldexp(rv.standard_normal(rows), re.integers(-30, 31, rows))
     return keys, vals
+
+
+def decimal_columns(n: int, ncols: int = 6, salt: int = 0):
+    """Decimal-like float64 columns: x log-uniform in [1, 1e6], rounded to
+    two decimals (round(x * 100) / 100)."""
+    rng = rng_for(5, 0, salt)
+    x = np.exp(rng.uniform(0.0, np.log(1e6), (ncols, n)))
+    return np.round(x * 100.0) / 100.0
+
+
+def served_queries(count: int = 128, min_rows: int = 10_000, max_rows: int = 50_000_000, min_groups: int = 4,
+                   max_groups: int = 1 << 20, salt: int = 0):
+    """Sizes of a stream of GroupBy queries: rows log-uniform in
+    [min_rows, max_rows], groups log-uniform in [min_groups, max_groups],
+    and unit-rate exponential inter-arrival gaps (scale them by 1/rate for
+    a Poisson process of that rate)."""
+    r = rng_for(5, 1, salt)
+    rows = np.exp(r.uniform(np.log(min_rows), np.log(max_rows), count)).astype(np.int64)
+    groups = np.exp(r.uniform(np.log(min_groups), np.log(max_groups), count)).astype(np.int64)
+    gaps = r.exponential(1.0, count)
+    return rows, groups, gaps
+
+
+def served_keys(n: int, groups: int, query: int, salt: int = 0):
+    """int32 keys U[0, groups) of one served query."""
+    return rng_for(5, 2, salt * 1000003 + query).integers(0, groups, n, dtype=np.int32)
+
+
+# The four aggregates of a served query: SUM(c0), SUM(c1), SUM(c2*c3), SUM(c4*c5).
+SERVED_AGGS = ((0, None), (1, None), (2, 3), (4, 5))

@@ -89,3 +89,25 @@ def test_batch_workspace_and_validation_without_gpu(lib):
                                    ctypes.byref(plan), None) == _lib.REPRO_EINVAL
     assert lib.repro_batch_prepare(jobs, len(ok), _lib.I32, _lib.F64, _lib.F64, None, ctypes.c_void_p(257), need,
                                    ctypes.byref(plan), None) == _lib.REPRO_EINVAL
+
+
+def test_query_bytes_without_gpu(lib):
+    q = _lib.Query()
+    q.keys = 0x1000
+    for i in range(6):
+        q.cols[i] = 0x100000 * (i + 1)
+    q.n, q.num_groups, q.L, q.naggs = 1_000_000, 1000, 2, 4
+    for i, (a, b) in enumerate(((0, -1), (1, -1), (2, 3), (4, 5))):
+        q.agg_a[i], q.agg_b[i], q.out[i] = a, b, 0x9000000 + 0x10000 * i
+    cfg = _lib.ServerConfig(4, 1 << 20)
+    need = lib.repro_query_bytes(ctypes.byref(q), ctypes.byref(cfg))
+    # four states, two product columns (8 B per row each), one chunk's workspace
+    assert need >= 4 * lib.repro_state_bytes(1000, _lib.F64, 2) + 2 * 8 * 1_000_000
+    q.naggs = 5
+    assert lib.repro_query_bytes(ctypes.byref(q), ctypes.byref(cfg)) == 0
+    q.naggs = 4
+    q.cols[5] = None  # a product aggregate without its column
+    assert lib.repro_query_bytes(ctypes.byref(q), ctypes.byref(cfg)) == 0
+    srv = ctypes.c_void_p()
+    assert lib.repro_server_create(ctypes.c_void_p(257), 1 << 20, ctypes.byref(cfg), ctypes.byref(srv)) == \
+        _lib.REPRO_EINVAL  # misaligned arena, rejected before any GPU call

@@ -1,0 +1,133 @@
+"""Serving: queries admitted by memory into a fixed set of slots, their
+states resident and fed chunk by chunk; every result must be bit-identical
+alone and in the mix, and equal to the oracle (needs a GPU)."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1802_09883_amd import workloads as WL
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1802_09883_amd import api
+else:  # collected on CPU-only hosts, never run there
+    api = None
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def make_queries(count, max_rows, max_groups, salt):
+    rows, groups, gaps = WL.served_queries(count, min_rows=10_000, max_rows=max_rows, max_groups=max_groups, salt=salt)
+    pool = WL.decimal_columns(int(rows.max()), 6, salt=salt)
+    pool_t = [torch.from_numpy(np.ascontiguousarray(c)).cuda() for c in pool]
+    host, specs = [], []
+    rng = np.random.default_rng(salt)
+    for q, (n, G) in enumerate(zip(rows, groups)):
+        off = int(rng.integers(0, int(rows.max()) - int(n) + 1))
+        keys = WL.served_keys(int(n), int(G), q, salt)
+        host.append((keys, off, int(n), int(G)))
+        specs.append(api.QuerySpec(torch.from_numpy(keys).cuda(), [c[off:off + n] for c in pool_t], int(G),
+                                   WL.SERVED_AGGS, L=2))
+    return pool, host, specs, gaps
+
+
+def oracle_sums(pool, keys, off, n, G, L=2):
+    cols = [c[off:off + n] for c in pool]
+    outs = []
+    for a, b in WL.SERVED_AGGS:
+        v = cols[a] if b is None else cols[a] * cols[b]  # one IEEE rounding, as on the device
+        st, status = O.groupby_sum(keys, v, G, L, True, threads=8)
+        assert status == 0
+        outs.append(O.finalize(st, G, L))
+    return outs
+
+
+def run_server(specs, arrival_gaps=None, slots=4, arena_bytes=4 << 30, chunk_rows=300_000, timeout=120.0):
+    srv = api.Server(arena_bytes, slots=slots, chunk_rows=chunk_rows)
+    try:
+        t0 = srv.clock()
+        arr = t0 + (np.cumsum(arrival_gaps) if arrival_gaps is not None else np.zeros(len(specs)))
+        done, i, peak = {}, 0, 0
+        while len(done) < len(specs):
+            now = srv.clock()
+            while i < len(specs) and arr[i] <= now:
+                assert srv.submit(specs[i]) == i
+                i += 1
+            comp, nq, nr = srv.poll()
+            peak = max(peak, nr)
+            for t, tm in comp:
+                done[t] = tm
+            assert srv.clock() - t0 < timeout, "server did not finish"
+        torch.cuda.synchronize()
+        return [done[k] - arr[k] for k in range(len(specs))], peak
+    finally:
+        srv.close()
+
+
+def test_each_result_same_alone_and_in_the_mix():
+    pool, host, specs, gaps = make_queries(14, max_rows=1_500_000, max_groups=1 << 20, salt=1)
+    say(f"case serve mix: {len(specs)} queries, rows {[h[2] for h in host]}, groups {[h[3] for h in host]}")
+    alone = []
+    for s in specs:
+        run_server([s], slots=1)
+        alone.append([o.clone() for o in s.out])
+    for s in specs:
+        for o in s.out:
+            o.fill_(float("nan"))
+    # in the mix: arrivals 50 us apart on average, 4 slots, chunked states
+    lat, peak = run_server(specs, arrival_gaps=gaps * 50e-6, slots=4)
+    say(f"mix: peak running {peak}, latencies ms {np.round(np.array(lat) * 1e3, 2)}")
+    assert peak >= 2, "queries should have overlapped"
+    for q, (s, a, (keys, off, n, G)) in enumerate(zip(specs, alone, host)):
+        ref = oracle_sums(pool, keys, off, n, G)
+        for k, (o, b, r) in enumerate(zip(s.out, a, ref)):
+            got = o.cpu().numpy()
+            assert np.array_equal(got.view(np.uint8), b.cpu().numpy().view(np.uint8)), \
+                f"query {q} aggregate {k}: differs between alone and in the mix"
+            assert np.array_equal(got.view(np.uint8), r.view(np.uint8)), f"query {q} aggregate {k}: differs from oracle"
+
+
+def test_admission_waits_for_memory():
+    pool, host, specs, gaps = make_queries(6, max_rows=400_000, max_groups=5000, salt=2)
+    srv = api.Server(1 << 30, slots=8)
+    need = max(srv.query_bytes(s) for s in specs)
+    srv.close()
+    arena = int(need * 2.2) // 256 * 256  # room for about two queries at a time
+    lat, peak = run_server(specs, slots=8, arena_bytes=arena)
+    assert 1 <= peak <= 2, f"memory admits at most two queries, saw {peak}"
+    for s, (keys, off, n, G) in zip(specs, host):
+        for o, r in zip(s.out, oracle_sums(pool, keys, off, n, G)):
+            assert np.array_equal(o.cpu().numpy(), r)
+
+
+def test_invalid_and_oversized_queries_are_rejected():
+    keys = torch.zeros(100, dtype=torch.int32, device="cuda")
+    col = torch.ones(100, dtype=torch.float64, device="cuda")
+    srv = api.Server(1 << 20, slots=2)
+    try:
+        with pytest.raises(ValueError):
+            srv.submit(api.QuerySpec(keys, [col], 4, [(0, None)] * 5))  # too many aggregates
+        with pytest.raises(ValueError):
+            srv.submit(api.QuerySpec(keys, [col], 4, [(3, None)]))  # missing column
+        with pytest.raises(ValueError):
+            srv.submit(api.QuerySpec(keys, [col], 1 << 20, [(0, None)]))  # states larger than the arena
+        spec = api.QuerySpec(keys, [col], 4, [(0, None), (0, 0)])
+        assert srv.submit(spec) == 0
+        while True:
+            done, nq, nr = srv.poll()
+            if done:
+                break
+            time.sleep(0.001)
+        torch.cuda.synchronize()
+        assert spec.out[0].cpu().tolist() == [100.0, 0.0, 0.0, 0.0]
+        assert spec.out[1].cpu().tolist() == [100.0, 0.0, 0.0, 0.0]
+    finally:
+        srv.close()
