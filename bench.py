@@ -65,6 +65,8 @@ CONFIGS = {
                   "4 SUM aggregates over 6 decimal-like f64 columns (SUM c0, SUM c1, SUM c2*c3, SUM c4*c5), rows "
                   "log-uniform 1e4..5e7 ({n} in all), groups log-uniform 4..2^20, int32 keys, repro<double,2>, "
                   "{slots} slots, memory-admitted"),
+    "sum": dict(rows=200_000_000, groups=1, L=3, desc="ungrouped sum: {n} f64 values 2^U(-60,60) with exact "
+                "cancellation pairs (the lowcard f64 column), repro<double,{L}>"),
     "batched": dict(rows=0, groups=0, L=0, desc="batched: {jobs} independent GroupBy-SUM jobs in one persistent "
                     "launch (graph-replayed), rows log-uniform 1e3..1e7 ({n} in all), groups log-uniform 1..2^16, "
                     "int32 keys, f64 N(0,1)*2^U(-30,30), repro<double,L>, L in {{2,3}}, autotuned"),
@@ -106,6 +108,8 @@ def main():
         return bench_batched(args)
     if args.config == "serve":
         return bench_serve(args)
+    if args.config == "sum":
+        return bench_sum(args)
 
     import torch
 
@@ -301,6 +305,69 @@ def bench_batched(args):
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_batch<int32,f64,f64> (persistent, with its reset kernel)",
+                     "kernel_ms": round(ms_dev, 4), "alg_bytes_per_launch": alg},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def bench_sum(args):
+    """Ungrouped reproducible sum: one step = reset the state, sum the column,
+    finalise (the profile events bracket nothing here: HIP events on the
+    stream around the whole step)."""
+    import torch
+
+    from paper_1802_09883_amd import api, workloads
+
+    cfg = CONFIGS["sum"]
+    n = args.rows or cfg["rows"]
+    L = cfg["L"]
+    _, v64, _ = workloads.lowcard(n=n, groups=1024, with_f32=False)
+    dev = torch.device("cuda:0")
+    v = torch.from_numpy(v64).to(dev)
+    st = api.state_init(1, L)
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+
+    def step():
+        api.state_reset(st, 1, L)
+        api.sum(v, L, state=st)
+        api.finalize(st, 1, L, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms_dev = e0.elapsed_time(e1) / args.steps
+    pl = torch.zeros(1, dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        torch.sum(v, dim=0, out=pl[0])
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    alg = n * 8
+    ach = alg / (ms_dev * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(np.zeros(n, np.int32), [v64], 1, L, args.cpu_seconds)
+    rec = {
+        "metric": "repro GroupBy-SUM rows/s", "value": n / (ms * 1e-3), "unit": "rows/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg["desc"].format(n=n, L=L), "name": "sum", "rows": n, "groups": 1, "L": L,
+                   "parallelism": "single GPU"},
+        "step_hbm_frac": round(ach / HBM_PEAK_GBS, 4),
+        "plain_fp64_atomic": {"ms_per_step": round(plain_ms, 4), "slowdown": round(ms / plain_ms, 3),
+                              "note": "torch.sum (non-reproducible tree reduction) on the same column"},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_sum<f64,f64,L=3> + k_sum_merge + state reset + finalize (whole step)",
                      "kernel_ms": round(ms_dev, 4), "alg_bytes_per_launch": alg},
         "cpu_baseline": cpu,
     }

@@ -134,6 +134,18 @@ int repro_plain_groupby_sum(const void* keys, repro_key_t kt, const void* values
                             int64_t num_groups, double* out, uint32_t* status, hipStream_t stream);
 
 /*
+ * Ungrouped reproducible sum (RSum over a whole column, Sec. III-C/III-D):
+ * state (a one-group state buffer, repro_state_bytes(1, T, L)) += the sum
+ * of values[0..n).  Bits equal those of repro_groupby_sum with every key 0
+ * and one group; no keys are read.  values as for repro_groupby_sum;
+ * workspace >= repro_sum_workspace_bytes(n, L) bytes, 256-byte aligned.
+ * REPRO_EINVAL also for n beyond 2^35.
+ */
+size_t repro_sum_workspace_bytes(int64_t n, int L);
+int repro_sum(const void* values, repro_scalar_t vt, int64_t n, repro_scalar_t T, int L, void* state,
+              void* workspace, size_t workspace_bytes, uint32_t* status, hipStream_t stream);
+
+/*
  * ------------------------------------------------------------ batches
  *
  * Many independent GroupBy-SUMs (jobs) in one persistent kernel launch.

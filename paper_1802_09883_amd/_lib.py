@@ -93,6 +93,10 @@ def load():
     lib.repro_batch_launch.argtypes = [bp, vp, vp]
     lib.repro_batch_tune.restype = ctypes.c_int
     lib.repro_batch_tune.argtypes = [bj, i32, i32, i32, i32, vp, sz, bc, ctypes.POINTER(ctypes.c_float), vp]
+    lib.repro_sum_workspace_bytes.restype = sz
+    lib.repro_sum_workspace_bytes.argtypes = [i64, i32]
+    lib.repro_sum.restype = ctypes.c_int
+    lib.repro_sum.argtypes = [vp, i32, i64, i32, i32, vp, vp, sz, vp, vp]
     qp, scp = ctypes.POINTER(Query), ctypes.POINTER(ServerConfig)
     lib.repro_query_bytes.restype = sz
     lib.repro_query_bytes.argtypes = [qp, scp]

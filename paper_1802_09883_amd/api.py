@@ -104,6 +104,23 @@ def groupby_sum(keys: torch.Tensor, values: torch.Tensor, num_groups: int, L: in
     return states
 
 
+def sum(values: torch.Tensor, L: int = 2, T=torch.float64, state: torch.Tensor | None = None,
+        status: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Ungrouped reproducible sum of a column into a one-group state
+    (returned; a fresh one if none is given)."""
+    lib = _lib.load()
+    if values.dtype not in _SCALAR or values.dim() != 1 or not values.is_cuda:
+        raise TypeError("values: 1-D float32/float64 device tensor")
+    values = values.contiguous()
+    if state is None:
+        state = state_init(1, L, T, values.device, stream)
+    need = int(lib.repro_sum_workspace_bytes(values.numel(), L))
+    ws = _workspace(need, values.device, stream) if need else None
+    _lib.check(lib.repro_sum(_vp(values), _SCALAR[values.dtype], values.numel(), _T(T), L, _vp(state), _vp(ws),
+                             need, _vp(status), _stream(values.device, stream)), "sum")
+    return state
+
+
 def merge(dst: torch.Tensor, src: torch.Tensor, num_groups: int, L: int = 2, T=torch.float64, stream=None):
     """dst += src group by group (operator+=(repro)); returns dst."""
     lib = _lib.load()

@@ -96,15 +96,24 @@ def test_each_result_same_alone_and_in_the_mix():
 
 
 def test_admission_waits_for_memory():
-    pool, host, specs, gaps = make_queries(6, max_rows=400_000, max_groups=5000, salt=2)
-    srv = api.Server(1 << 30, slots=8)
-    need = max(srv.query_bytes(s) for s in specs)
-    srv.close()
-    arena = int(need * 2.2) // 256 * 256  # room for about two queries at a time
+    """Six queries of one size, all submitted at once, into an arena that
+    holds two of them: never more than two run, and all finish correctly."""
+    n, G = 300_000, 3000
+    pool = WL.decimal_columns(n, 6, salt=2)
+    pool_t = [torch.from_numpy(np.ascontiguousarray(c)).cuda() for c in pool]
+    host, specs = [], []
+    for q in range(6):
+        keys = WL.served_keys(n, G, q, salt=2)
+        host.append(keys)
+        specs.append(api.QuerySpec(torch.from_numpy(keys).cuda(), pool_t, G, WL.SERVED_AGGS, L=2))
+    probe = api.Server(1 << 30, slots=8, chunk_rows=300_000)
+    need = probe.query_bytes(specs[0])
+    probe.close()
+    arena = (need // 256 + 1) * 256 * 2 + need // 2  # two fit, three do not
     lat, peak = run_server(specs, slots=8, arena_bytes=arena)
-    assert 1 <= peak <= 2, f"memory admits at most two queries, saw {peak}"
-    for s, (keys, off, n, G) in zip(specs, host):
-        for o, r in zip(s.out, oracle_sums(pool, keys, off, n, G)):
+    assert peak == 2, f"memory admits exactly two queries at a time, saw {peak}"
+    for s, keys in zip(specs, host):
+        for o, r in zip(s.out, oracle_sums(pool, keys, 0, n, G)):
             assert np.array_equal(o.cpu().numpy(), r)
 
 
