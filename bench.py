@@ -65,6 +65,8 @@ CONFIGS = {
                   "4 SUM aggregates over 6 decimal-like f64 columns (SUM c0, SUM c1, SUM c2*c3, SUM c4*c5), rows "
                   "log-uniform 1e4..5e7 ({n} in all), groups log-uniform 4..2^20, int32 keys, repro<double,2>, "
                   "{slots} slots, memory-admitted"),
+    "float": dict(rows=200_000_000, groups=1024, L=2, desc="float accumulators: {n} rows, int32 keys U[0,{G}), "
+                  "f32 column 2^U(-60,60) with exact cancellation pairs, repro<float,{L}>"),
     "sum": dict(rows=200_000_000, groups=1, L=3, desc="ungrouped sum: {n} f64 values 2^U(-60,60) with exact "
                 "cancellation pairs (the lowcard f64 column), repro<double,{L}>"),
     "batched": dict(rows=0, groups=0, L=0, desc="batched: {jobs} independent GroupBy-SUM jobs in one persistent "
@@ -80,6 +82,9 @@ def make_columns(workloads, name, n, G):
     if name == "highcard":
         keys, v = workloads.highcard(n=n, groups=G)
         return keys, [("f64", v)]
+    if name == "float":
+        keys, _, v32 = workloads.lowcard(n=n, groups=G)
+        return keys, [("f32", v32)]
     keys, v = workloads.plain(n=n, groups=G)
     return keys, [("f64", v)]
 
@@ -125,7 +130,7 @@ def main():
     dev = torch.device("cuda:0")
     kt = torch.from_numpy(keys).to(dev)
     vts = [(name, torch.from_numpy(v).to(dev)) for name, v in cols]
-    T = torch.float64
+    T = torch.float32 if args.config == "float" else torch.float64
     states = [api.state_init(G, L, T, dev) for _ in vts]
     outs = [torch.empty(G, dtype=T, device=dev) for _ in vts]
     wsb = max(api.workspace_bytes(n, G, kt.dtype, v.dtype, L, T) for _, v in vts)
@@ -187,6 +192,7 @@ def main():
     k0 = float(np.mean(kcol[0]))
     ach_gbs = alg_k0 / (k0 * 1e-3) / 1e9
     kname = {"lowcard": "k_agg_lds<int32,f64,f64,L=3>", "plain": "k_agg_lds<int32,f64,f64,L=2>",
+             "float": "k_agg_lds<int32,f32,f32,L=2>",
              "highcard": "k_agg_part<f64,f64,L=2> (after partitioning)"}[args.config]
     roofline = {"bound": "hbm", "achieved": round(ach_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach_gbs / HBM_PEAK_GBS, 4),
@@ -200,7 +206,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(keys, [v for _, v in cols], G, L, args.cpu_seconds)
+        cpu = cpu_baseline(keys, [v for _, v in cols], G, L, args.cpu_seconds, T64=(args.config != "float"))
 
     rows_per_s = n / (ms_step * 1e-3)
     rec = {
@@ -214,7 +220,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if args.config == "float" else "f64",
         "data": "synthetic",
         "config": {"workload": cfg["desc"].format(n=n, G=G, L=L), "name": args.config, "rows": n, "groups": G,
                    "L": L, "columns": [name for name, _ in vts], "parallelism": "single GPU"},
@@ -529,7 +535,7 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 3}), flush=True)
 
 
-def cpu_baseline(keys, cols, G, L, seconds):
+def cpu_baseline(keys, cols, G, L, seconds, T64=True):
     """The CPU oracle (threaded over row chunks, then merged) on a bounded
     prefix of the same rows, every column, finalised: rows/s."""
     from oracle import oracle
@@ -539,8 +545,8 @@ def cpu_baseline(keys, cols, G, L, seconds):
     def run(m):
         t0 = time.perf_counter()
         for v in cols:
-            st, _ = oracle.groupby_sum(keys[:m], v[:m], G, L, True, threads=cores)
-            oracle.finalize(st, G, L)
+            st, _ = oracle.groupby_sum(keys[:m], v[:m], G, L, T64, threads=cores)
+            oracle.finalize(st, G, L, T64)
         return time.perf_counter() - t0
 
     probe = min(len(keys), 2_000_000)

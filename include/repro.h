@@ -146,6 +146,25 @@ int repro_sum(const void* values, repro_scalar_t vt, int64_t n, repro_scalar_t T
               void* workspace, size_t workspace_bytes, uint32_t* status, hipStream_t stream);
 
 /*
+ * Exact row counts per group (COUNT(*) of the GroupBy, Sec. II-A):
+ * counts[g] += number of rows with key g (int64, accumulated into; integer
+ * additions, so order-free).  Bad keys set REPRO_ERR_KEY.
+ */
+int repro_groupby_count(const void* keys, repro_key_t kt, int64_t n, int64_t num_groups, int64_t* counts,
+                        uint32_t* status, hipStream_t stream);
+
+/*
+ * Aggregates derived from reproducible sums (AVG, VAR, STDDEV computed from
+ * SUM, as Sec. I notes they can be): from the finalised SUM(x), SUM(x*x)
+ * (float64) and COUNT of every group, in a fixed order of IEEE operations,
+ * no fused multiply-add:
+ *   avg = s / c;  var_samp = (q - s * avg) / (c - 1);  stddev = sqrt(var).
+ * NaN where c = 0 (avg) or c < 2 (var, stddev).  Any output may be NULL.
+ */
+int repro_derive_stats(const double* sum, const double* sumsq, const int64_t* count, int64_t num_groups, double* avg,
+                       double* var_samp, double* stddev_samp, hipStream_t stream);
+
+/*
  * ------------------------------------------------------------ batches
  *
  * Many independent GroupBy-SUMs (jobs) in one persistent kernel launch.

@@ -97,6 +97,10 @@ def load():
     lib.repro_sum_workspace_bytes.argtypes = [i64, i32]
     lib.repro_sum.restype = ctypes.c_int
     lib.repro_sum.argtypes = [vp, i32, i64, i32, i32, vp, vp, sz, vp, vp]
+    lib.repro_groupby_count.restype = ctypes.c_int
+    lib.repro_groupby_count.argtypes = [vp, i32, i64, i64, vp, vp, vp]
+    lib.repro_derive_stats.restype = ctypes.c_int
+    lib.repro_derive_stats.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
     qp, scp = ctypes.POINTER(Query), ctypes.POINTER(ServerConfig)
     lib.repro_query_bytes.restype = sz
     lib.repro_query_bytes.argtypes = [qp, scp]

@@ -121,6 +121,33 @@ def sum(values: torch.Tensor, L: int = 2, T=torch.float64, state: torch.Tensor |
     return state
 
 
+def groupby_count(keys: torch.Tensor, num_groups: int, counts=None, status=None, stream=None) -> torch.Tensor:
+    """Exact int64 row counts per group (accumulated into ``counts``)."""
+    lib = _lib.load()
+    keys = keys.contiguous()
+    if counts is None:
+        counts = torch.zeros(num_groups, dtype=torch.int64, device=keys.device)
+    _lib.check(lib.repro_groupby_count(_vp(keys), _KEY[keys.dtype], keys.numel(), num_groups, _vp(counts),
+                                       _vp(status), _stream(keys.device, stream)), "groupby_count")
+    return counts
+
+
+def groupby_stats(keys: torch.Tensor, values: torch.Tensor, num_groups: int, L: int = 2, stream=None):
+    """Reproducible AVG, sample VAR and sample STDDEV per group, derived from
+    the reproducible SUM(x), SUM(x*x) (x*x rounded once per row) and the
+    exact COUNT.  Returns a dict of float64 tensors (and the inputs)."""
+    lib = _lib.load()
+    values = values.to(torch.float64)
+    sq = values * values
+    s = finalize(groupby_sum(keys, values, num_groups, L, stream=stream), num_groups, L, stream=stream)
+    q = finalize(groupby_sum(keys, sq, num_groups, L, stream=stream), num_groups, L, stream=stream)
+    c = groupby_count(keys, num_groups, stream=stream)
+    avg, var, sd = (torch.empty(num_groups, dtype=torch.float64, device=keys.device) for _ in range(3))
+    _lib.check(lib.repro_derive_stats(_vp(s), _vp(q), _vp(c), num_groups, _vp(avg), _vp(var), _vp(sd),
+                                      _stream(keys.device, stream)), "derive_stats")
+    return {"sum": s, "sumsq": q, "count": c, "avg": avg, "var_samp": var, "stddev_samp": sd}
+
+
 def merge(dst: torch.Tensor, src: torch.Tensor, num_groups: int, L: int = 2, T=torch.float64, stream=None):
     """dst += src group by group (operator+=(repro)); returns dst."""
     lib = _lib.load()

@@ -1,4 +1,5 @@
-// repro_sum.hip -- ungrouped reproducible sum into repro<T,L> (librepro,
+// repro_sum.hip -- ungrouped reproducible sum into repro<T,L>, exact
+// per-group counts and aggregates derived from reproducible sums (librepro,
 // gfx950).
 //
 // Paper: Mueller, Arteaga, Hoefler, Alonso, "Reproducible Floating-Point
@@ -254,9 +255,89 @@ int sum_L(int L, const void* values, int64_t n, void* state, unsigned char* ws, 
     }
 }
 
+// Exact row counts per group: an LDS histogram per workgroup for the
+// groups that fit, then one integer atomic per group and workgroup (integer
+// addition is exact and associative, so the counts do not depend on order).
+constexpr int CNT_BLOCK = 256;
+constexpr int CNT_LDS_GROUPS = 16384;
+
+template <class KT>
+__global__ void __launch_bounds__(CNT_BLOCK) k_count(const KT* __restrict__ keys, int64_t n, int64_t G,
+                                                     unsigned long long* __restrict__ counts,
+                                                     uint32_t* __restrict__ status) {
+    __shared__ unsigned int h[CNT_LDS_GROUPS];
+    const bool lds = G <= CNT_LDS_GROUPS;
+    if (lds)
+        for (int g = threadIdx.x; g < G; g += CNT_BLOCK) h[g] = 0;
+    __syncthreads();
+    uint32_t err = 0;
+    for (int64_t i = (int64_t)blockIdx.x * CNT_BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * CNT_BLOCK) {
+        const int64_t k = (int64_t)keys[i];
+        if ((uint64_t)k >= (uint64_t)G) {
+            err |= ERR_KEY;
+        } else if (lds) {
+            atomicAdd(&h[k], 1u);
+        } else {
+            atomicAdd(&counts[k], 1ull);
+        }
+    }
+    __syncthreads();
+    if (lds)
+        for (int g = threadIdx.x; g < G; g += CNT_BLOCK)
+            if (h[g]) atomicAdd(&counts[g], (unsigned long long)h[g]);
+    report(status, err);
+}
+
+// AVG, sample VAR and sample STDDEV of every group from its reproducible
+// SUM(x), SUM(x*x) and exact COUNT, in a fixed order of IEEE operations
+// (no contraction): the results are as reproducible as their inputs.
+// Groups with no row give NaN for AVG; fewer than two rows give NaN for
+// VAR and STDDEV.
+__global__ void __launch_bounds__(256) k_derive(const double* __restrict__ sum, const double* __restrict__ sumsq,
+                                                const long long* __restrict__ cnt, int64_t G,
+                                                double* __restrict__ avg, double* __restrict__ var,
+                                                double* __restrict__ sd) {
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < G; g += (int64_t)gridDim.x * 256) {
+        const double c = (double)cnt[g];  // exact below 2^53 rows
+        const double s = sum[g], q = sumsq[g];
+        const double m = s / c;
+        const double u = q - s * m;
+        const double v = u / (c - 1.0);
+        if (avg) avg[g] = cnt[g] > 0 ? m : __builtin_nan("");
+        if (var) var[g] = cnt[g] > 1 ? v : __builtin_nan("");
+        if (sd) sd[g] = cnt[g] > 1 ? sqrt(v) : __builtin_nan("");
+    }
+}
+
 }  // namespace
 
 extern "C" {
+
+int repro_groupby_count(const void* keys, repro_key_t kt, int64_t n, int64_t num_groups, int64_t* counts,
+                        uint32_t* status, hipStream_t stream) {
+    if (n < 0 || num_groups < 1 || num_groups > INT32_MAX || !counts || (kt != REPRO_I32 && kt != REPRO_I64))
+        return REPRO_EINVAL;
+    if (n == 0) return REPRO_OK;
+    if (!keys) return REPRO_EINVAL;
+    const unsigned grid = (unsigned)std::min<int64_t>(2048, (n + CNT_BLOCK * 8 - 1) / (CNT_BLOCK * 8));
+    unsigned long long* c = reinterpret_cast<unsigned long long*>(counts);
+    if (kt == REPRO_I32)
+        hipLaunchKernelGGL(k_count<int32_t>, dim3(grid), dim3(CNT_BLOCK), 0, stream,
+                           static_cast<const int32_t*>(keys), n, num_groups, c, status);
+    else
+        hipLaunchKernelGGL(k_count<int64_t>, dim3(grid), dim3(CNT_BLOCK), 0, stream,
+                           static_cast<const int64_t*>(keys), n, num_groups, c, status);
+    return hipGetLastError() == hipSuccess ? REPRO_OK : REPRO_EHIP;
+}
+
+int repro_derive_stats(const double* sum, const double* sumsq, const int64_t* count, int64_t num_groups, double* avg,
+                       double* var_samp, double* stddev_samp, hipStream_t stream) {
+    if (!sum || !sumsq || !count || num_groups < 1 || num_groups > INT32_MAX) return REPRO_EINVAL;
+    const unsigned grid = (unsigned)std::min<int64_t>(4096, (num_groups + 255) / 256);
+    hipLaunchKernelGGL(k_derive, dim3(grid), dim3(256), 0, stream, sum, sumsq,
+                       reinterpret_cast<const long long*>(count), num_groups, avg, var_samp, stddev_samp);
+    return hipGetLastError() == hipSuccess ? REPRO_OK : REPRO_EHIP;
+}
 
 size_t repro_sum_workspace_bytes(int64_t n, int L) {
     SumPlan p;

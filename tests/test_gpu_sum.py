@@ -123,3 +123,43 @@ def test_accuracy_within_bound(dist, n):
         rows.append((L, float(err), float(bound), abs(fin - float(ex))))
     say(f"accuracy {dist} n={n}: " + "; ".join(f"L={L} level error {e:.3e} (bound {b:.3e}), final {f:.3e}"
                                               for L, e, b, f in rows))
+
+
+def test_counts_and_derived_statistics():
+    """COUNT is exact; AVG / VAR / STDDEV derived from reproducible sums are
+    bit-identical to the same formula applied to the oracle's sums, and do
+    not change with the row order."""
+    rng = np.random.default_rng(9)
+    n, G = 2_000_003, 5000
+    keys = rng.integers(0, G, n).astype(np.int32)
+    keys[:10] = G - 1  # group G-1 has rows; make one group empty and one with a single row
+    keys[keys == 7] = 8
+    keys[11] = 7
+    vals = np.round(np.exp(rng.uniform(0, np.log(1e6), n)) * 100) / 100
+    out = api.groupby_stats(torch.from_numpy(keys).cuda(), torch.from_numpy(vals).cuda(), G, L=2)
+    cnt = np.bincount(keys, minlength=G)
+    assert np.array_equal(out["count"].cpu().numpy(), cnt)
+    s_ref = O.finalize(O.groupby_sum(keys, vals, G, 2, threads=8)[0], G, 2)
+    q_ref = O.finalize(O.groupby_sum(keys, vals * vals, G, 2, threads=8)[0], G, 2)
+    assert np.array_equal(out["sum"].cpu().numpy(), s_ref) and np.array_equal(out["sumsq"].cpu().numpy(), q_ref)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        c = cnt.astype(np.float64)
+        m = s_ref / c
+        v = (q_ref - s_ref * m) / (c - 1.0)
+    m = np.where(cnt > 0, m, np.nan)
+    v = np.where(cnt > 1, v, np.nan)
+    got_m, got_v, got_s = (out[k].cpu().numpy() for k in ("avg", "var_samp", "stddev_samp"))
+    assert np.array_equal(got_m, m, equal_nan=True)
+    assert np.array_equal(got_v, v, equal_nan=True)
+    # sqrt: within one ulp of the correctly rounded root (the device routine
+    # is deterministic; its last bit is not part of the contract)
+    want_s = np.sqrt(v)
+    ok = np.isnan(want_s) == np.isnan(got_s)
+    fin = ~np.isnan(want_s)
+    assert ok.all() and np.all(np.abs(got_s[fin] - want_s[fin]) <= np.spacing(want_s[fin]))
+    assert np.isnan(got_v[7]) and not np.isnan(got_m[7])  # one row: AVG defined, VAR not
+    # another order of the same rows: the same bits
+    perm = rng.permutation(n)
+    out2 = api.groupby_stats(torch.from_numpy(keys[perm]).cuda(), torch.from_numpy(vals[perm]).cuda(), G, L=2)
+    for k in ("avg", "var_samp", "stddev_samp"):
+        assert np.array_equal(out2[k].cpu().numpy().view(np.uint64), out[k].cpu().numpy().view(np.uint64))
