@@ -106,8 +106,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on a single MI355X "
+              "(sharding over several GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.config == "batched":
         return bench_batched(args)

@@ -198,3 +198,36 @@ def test_batch_full_size_512_jobs_sampled():
     pick = sorted(set(range(0, len(jobs), 8)) | set(np.argsort(rows)[-4:].tolist()) |
                   set(np.argsort(groups)[-4:].tolist()))
     check_jobs([jobs[i] for i in pick], [specs[i] for i in pick], [priors[i] for i in pick], 0, "full batch")
+
+
+@pytest.mark.parametrize("T64", [True, False])
+def test_batch_int64_keys_float_values_and_unaligned_columns(T64):
+    rng = np.random.default_rng([6, T64])
+    specs, jobs = [], []
+    for j in range(12):
+        n = int(rng.integers(1, 150_000))
+        G = int(np.exp(rng.uniform(0, np.log(20_000))))
+        L = int(rng.integers(1, 5))
+        keys = rng.integers(-2, G + 2, n + 1).astype(np.int64)  # a few bad keys
+        vals = np.ldexp(rng.standard_normal(n + 1), rng.integers(-40, 40, n + 1)).astype(np.float32)
+        kt, vt = dev(keys), dev(vals)
+        if j % 2:  # start one row in: columns not 16-byte aligned, scalar loads
+            kt, vt, keys, vals = kt[1:], vt[1:], keys[1:], vals[1:]
+        else:
+            kt, vt, keys, vals = kt[:n], vt[:n], keys[:n], vals[:n]
+        T = torch.float64 if T64 else torch.float32
+        st = torch.zeros(api.state_bytes(G, L, T), dtype=torch.uint8, device="cuda")
+        jobs.append(api.Job(kt, vt, G, L, st, torch.empty(G, dtype=T, device="cuda")))
+        specs.append((keys, vals, G, L))
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    api.batch_groupby_sum(jobs, T=torch.float64 if T64 else torch.float32, status=status)
+    torch.cuda.synchronize()
+    want = 0
+    for i, (job, (keys, vals, G, L)) in enumerate(zip(jobs, specs)):
+        ref, st = O.groupby_sum(keys, vals, G, L, T64)
+        want |= st
+        Sg, Cg = O.split_states(job.states.cpu().numpy(), G, L, T64)
+        So, Co = O.split_states(ref, G, L, T64)
+        assert np.array_equal(Sg.view(np.uint8), So.view(np.uint8)) and np.array_equal(Cg, Co), f"job {i}"
+        assert np.array_equal(job.out.cpu().numpy().view(np.uint8), O.finalize(ref, G, L, T64).view(np.uint8))
+    assert int(status.item()) == want and want & 1

@@ -140,3 +140,25 @@ def test_invalid_and_oversized_queries_are_rejected():
         assert spec.out[1].cpu().tolist() == [100.0, 0.0, 0.0, 0.0]
     finally:
         srv.close()
+
+
+def test_status_bits_and_empty_query():
+    rng = np.random.default_rng(12)
+    n, G = 50_000, 300
+    keys = rng.integers(0, G, n).astype(np.int32)
+    keys[::1000] = G + 5  # bad keys
+    cols = WL.decimal_columns(n, 2, salt=12)
+    cols[0][17] = np.nan
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    spec = api.QuerySpec(torch.from_numpy(keys).cuda(), [torch.from_numpy(c).cuda() for c in cols], G,
+                         [(0, None), (0, 1)], L=3, status=status)
+    empty = api.QuerySpec(torch.zeros(0, dtype=torch.int32, device="cuda"),
+                          [torch.zeros(0, dtype=torch.float64, device="cuda")] * 2, 7, [(0, None), (0, 1)], L=2)
+    run_server([spec, empty], slots=2)
+    assert int(status.item()) == 1 | 2
+    for o, v in zip(spec.out, (cols[0], cols[0] * cols[1])):
+        st, s = O.groupby_sum(keys, v, G, 3)
+        assert s == 3
+        assert np.array_equal(o.cpu().numpy(), O.finalize(st, G, 3))
+    for o in empty.out:
+        assert o.cpu().numpy().tolist() == [0.0] * 7
