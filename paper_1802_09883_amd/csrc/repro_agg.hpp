@@ -108,6 +108,12 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t x) {
     return x;
 }
 
+__device__ __forceinline__ long long wave_sum64(long long x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
 __device__ __forceinline__ void report(uint32_t* status, uint32_t err) {
     err = wave_or(err);
     if (status && err && (threadIdx.x & 63) == 0) atomicOr(status, err);
@@ -324,6 +330,28 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
     int quiet = 0;     // consecutive per-tile synchronisations without a raise
     bool ahead = false;  // this tile's tops were raised at the previous synchronisation
 
+    // Per-tile mode: when many lanes of a wave deposit into one group (skewed
+    // keys), that "hot" group (wave-uniform) is summed in registers and added
+    // to its bins with one atomic per level before the next synchronisation
+    // (its top, and so the units' alignment, only changes there).  Exact, so
+    // the bits are the same; it spares the serialised same-address atomics.
+    constexpr int HOT_MIN = 8;  // lanes of a wave on one group that make it hot
+    int hot = -1;
+    long long hacc[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) hacc[l] = 0;
+    auto flush_hot = [&]() {
+        if (EPOCH || hot < 0) return;  // uniform
+        unsigned char* w0 = smem + __umul24((uint32_t)hot, gstride);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const long long x = wave_sum64(hacc[l]);
+            if ((tid & 63) == 0 && x != 0)
+                atomicAdd(reinterpret_cast<unsigned long long*>(w0 + l * lstride), (unsigned long long)x);
+            hacc[l] = 0;
+        }
+    };
+
     // Synchronisation point: all deposits before it are done.  If a top was
     // raised since the last one, realign every group with P > TOP (its levels
     // move down by the rise, the lowest fall off: the level shift of Alg. 2)
@@ -471,6 +499,7 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
                 ahead = true;
             }
             int sp;
+            flush_hot();
             const bool moved = synchronise(sp);
             quiet = moved ? 0 : quiet + 1;
             if (EPOCH && quiet >= QUIET_TILES) epoch_left = EPOCH_TILES;
@@ -498,6 +527,13 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
             sh.flag[sync % 3] = 1;
             atomicAdd(&sh.spills[sync % 3], ns);
         }
+        if (!EPOCH) {
+            const int g0 = __builtin_amdgcn_readfirstlane(gi[0]);
+            if (g0 != hot && g0 != G && __popcll(__ballot(gi[0] == g0)) >= HOT_MIN) {
+                flush_hot();
+                hot = g0;
+            }
+        }
         // extract and deposit; skipped rows (trash slot G: errors, zeros, and
         // in slice mode the rows of other slices) issue no LDS atomics
 #pragma unroll
@@ -505,7 +541,10 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
             long long k[L];
             extract_from_hi<L>((AT)vc[i], hi_[i], k);
             unsigned char* w = smem + __umul24((uint32_t)gi[i], gstride) + lane_off;
-            if (gi[i] != G) {
+            if (!EPOCH && gi[i] == hot) {
+#pragma unroll
+                for (int l = 0; l < L; ++l) hacc[l] += k[l];
+            } else if (gi[i] != G) {
 #pragma unroll
                 for (int l = 0; l < L; ++l)
                     atomicAdd(reinterpret_cast<unsigned long long*>(w + l * lstride), (unsigned long long)k[l]);
@@ -530,6 +569,7 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
     }
     // final synchronisation: tops include every spilled row, bins aligned
     int sp;
+    flush_hot();
     synchronise(sp);
     return err;
 }
