@@ -174,6 +174,26 @@ def main():
     log(f"step {ms_step:.3f} ms; aggregation kernel " +
         ", ".join(f"{name} {np.mean(k):.3f} ms" for (name, _), k in zip(vts, kcol)))
 
+    # inputs small enough to stay in the 256 MB Infinity Cache between steps:
+    # also time single steps after streaming 1 GiB through the caches (cold)
+    cold_ms = None
+    in_bytes = kt.numel() * kt.element_size() + sum(v.numel() * v.element_size() for _, v in vts)
+    if in_bytes < (512 << 20):
+        flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        cold = []
+        for _ in range(args.steps):
+            flush.fill_(1.0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            step()
+            e1.record()
+            torch.cuda.synchronize()
+            cold.append(e0.elapsed_time(e1))
+        cold_ms = float(np.median(cold))
+        del flush
+        log(f"cold-cache step {cold_ms:.4f} ms (median of {args.steps})")
+
     for _ in range(args.warmup):
         plain_step()
     torch.cuda.synchronize()
@@ -225,6 +245,7 @@ def main():
         "config": {"workload": cfg["desc"].format(n=n, G=G, L=L), "name": args.config, "rows": n, "groups": G,
                    "L": L, "columns": [name for name, _ in vts], "parallelism": "single GPU"},
         "step_hbm_frac": round(alg_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "cold_cache_ms_per_step": round(cold_ms, 4) if cold_ms is not None else None,
         "plain_fp64_atomic": {"ms_per_step": round(plain_ms, 4), "slowdown": round(ms_step / plain_ms, 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,

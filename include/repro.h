@@ -302,7 +302,9 @@ int repro_server_submit(repro_server* srv, const repro_query* q, int64_t* ticket
  * memory and slot), then admits queued queries in order while they fit.
  * Writes up to `cap` completed tickets and their completion times (seconds
  * on the host's monotonic clock) and the counts of completed (in this call),
- * queued and running queries. */
+ * queued and running queries.  If enqueueing an admitted query's work fails
+ * (REPRO_EHIP), that query is dropped: its slot and memory are freed once
+ * what was enqueued has finished, and the error is returned. */
 int repro_server_poll(repro_server* srv, int64_t* tickets, double* times, int cap, int* ndone, int* nqueued,
                       int* nrunning);
 

@@ -276,7 +276,15 @@ int repro_server_poll(repro_server* s, int64_t* tickets, double* times, int cap,
         const repro_query q = p.q;
         s->queue.pop_front();
         const int rc = enqueue_query(s, *free_slot, q, ly);
-        if (rc != REPRO_OK) return rc;
+        if (rc != REPRO_OK) {
+            // drop the query: let what was enqueued finish before its memory
+            // and slot are reused, then report the error
+            (void)hipStreamSynchronize(free_slot->stream);
+            s->alloc.release(free_slot->off, free_slot->bytes);
+            free_slot->busy = false;
+            free_slot->ticket = -1;
+            return rc;
+        }
     }
     if (ndone) *ndone = done;
     if (nqueued) *nqueued = (int)s->queue.size();
