@@ -426,8 +426,10 @@ def bench_serve(args):
                                    workloads.SERVED_AGGS, L=2))
     arena = 24 << 30
 
+    qwg = int(os.environ.get("REPRO_QUERY_WG", "0"))  # persistent workgroups per query (0: all)
+
     def run(arrivals):
-        srv = api.Server(arena, slots=slots)
+        srv = api.Server(arena, slots=slots, query_workgroups=qwg)
         try:
             t0 = srv.clock()
             arr = t0 + arrivals

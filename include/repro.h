@@ -259,8 +259,9 @@ int repro_batch_tune(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
  * the resident states), then are finalised into the caller's outputs.
  * Admitted queries run on separate streams, so their work overlaps on the
  * device.  Every result is bit-identical to repro_groupby_sum of the same
- * expression column alone: admission order, concurrency and chunking do
- * not change a bit.
+ * expression column alone: admission order, concurrency, chunking and the
+ * execution path do not change a bit.  The server allocates pinned host
+ * memory for plan uploads (a few KiB per slot), no device memory.
  */
 #define REPRO_MAX_COLS 8
 #define REPRO_MAX_AGGS 4
@@ -281,6 +282,13 @@ typedef struct {
 typedef struct {
     int slots;           /* queries on the GPU at once (one stream each), 1..64 */
     int64_t chunk_rows;  /* rows added to a query's states per call (0: 16M)   */
+    int no_batch_path;   /* 0: a query whose groups fit one workgroup's LDS runs
+                            its aggregates as jobs of one persistent batch launch
+                            (its plan uploaded from pinned host memory); 1: every
+                            query uses repro_groupby_sum chunk by chunk          */
+    int query_workgroups;  /* on the batch path, persistent workgroups per query
+                              (0: as many as the GPU holds).  Fewer let queries
+                              of other slots run beside a long one           */
 } repro_server_config;
 
 typedef struct repro_server repro_server;

@@ -26,6 +26,7 @@
 #include "repro.h"
 #include "repro_agg.hpp"
 #include "repro_device.hpp"
+#include "repro_batch_internal.hpp"
 
 using namespace repro;
 
@@ -461,6 +462,67 @@ int launch_plan(const repro_batch_plan* p, uint32_t* status, hipStream_t st) {
 
 }  // namespace
 
+namespace repro {
+namespace batchx {
+
+bool plan_sizes(const repro_batch_job* jobs, int njobs, repro_key_t kt, repro_scalar_t vt, repro_scalar_t T,
+                const repro_batch_config* cfg, size_t* workspace_bytes, size_t* image_bytes) {
+    HostPlan hp;
+    if (!make_batch_plan(jobs, njobs, kt, vt, T, cfg, &hp)) return false;
+    *workspace_bytes = hp.lay.total;
+    *image_bytes = hp.lay.counters;
+    return true;
+}
+
+int plan_into(const repro_batch_job* jobs, int njobs, repro_key_t kt, repro_scalar_t vt, repro_scalar_t T,
+              const repro_batch_config* cfg, void* image, size_t image_cap, void* workspace, size_t workspace_bytes,
+              repro_batch_plan* plan) {
+    if (!plan) return REPRO_EINVAL;
+    HostPlan hp;
+    if (!make_batch_plan(jobs, njobs, kt, vt, T, cfg, &hp)) return REPRO_EINVAL;
+    if (!workspace || workspace_bytes < hp.lay.total || (uintptr_t)workspace % 256 != 0) return REPRO_EINVAL;
+    if (!image || image_cap < hp.lay.counters) return REPRO_EINVAL;
+    // the plan image: head, jobs, items (counters, spill words and partials
+    // are device-only, cleared or written by the kernels)
+    unsigned char* img = static_cast<unsigned char*>(image);
+    memset(img, 0, hp.lay.counters);
+    BatchHead hd;
+    memset(&hd, 0, sizeof(hd));
+    hd.nitems = (int)hp.items.size();
+    hd.njobs = njobs;
+    hd.ncounters = (int)hp.ncounters;
+    hd.off_jobs = (long long)hp.lay.jobs;
+    hd.off_items = (long long)hp.lay.items;
+    hd.off_counters = (long long)hp.lay.counters;
+    hd.off_spill = (long long)hp.lay.spill;
+    hd.off_partials = (long long)hp.lay.partials;
+    hd.zero_words = (long long)((hp.lay.partials - hp.lay.counters) / 8);
+    memcpy(img, &hd, sizeof(hd));
+    if (njobs) memcpy(img + hp.lay.jobs, hp.jobs.data(), hp.jobs.size() * sizeof(BatchJob));
+    if (!hp.items.empty()) memcpy(img + hp.lay.items, hp.items.data(), hp.items.size() * sizeof(BatchItem));
+    // dynamic LDS beyond 64 KiB must be allowed per kernel; done here, on the
+    // host and outside any graph capture of the launches
+    if (hp.lds > 64 * 1024 && hipFuncSetAttribute(pick_kernel(kt, vt, T), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  (int)hp.lds) != hipSuccess)
+        return REPRO_EHIP;
+    memset(plan, 0, sizeof(*plan));
+    plan->workspace = workspace;
+    plan->items = (int64_t)hp.items.size();
+    plan->grid = (int)std::min<int64_t>(BATCH_MAX_WG, std::max<int64_t>(1, plan->items));
+    plan->lds_bytes = (int)hp.lds;
+    plan->kt = kt;
+    plan->vt = vt;
+    plan->T = T;
+    return REPRO_OK;
+}
+
+int launch(const repro_batch_plan* plan, uint32_t* status, hipStream_t stream) { return launch_plan(plan, status, stream); }
+
+int slice_limit(int L) { return slice_cap(L, 0); }
+
+}  // namespace batchx
+}  // namespace repro
+
 extern "C" {
 
 size_t repro_batch_workspace_bytes(const repro_batch_job* jobs, int njobs, repro_key_t kt, repro_scalar_t vt,
@@ -473,42 +535,15 @@ size_t repro_batch_workspace_bytes(const repro_batch_job* jobs, int njobs, repro
 int repro_batch_prepare(const repro_batch_job* jobs, int njobs, repro_key_t kt, repro_scalar_t vt, repro_scalar_t T,
                         const repro_batch_config* cfg, void* workspace, size_t workspace_bytes,
                         repro_batch_plan* plan, hipStream_t stream) {
-    if (!plan) return REPRO_EINVAL;
-    HostPlan hp;
-    if (!make_batch_plan(jobs, njobs, kt, vt, T, cfg, &hp)) return REPRO_EINVAL;
-    if (!workspace || workspace_bytes < hp.lay.total || (uintptr_t)workspace % 256 != 0) return REPRO_EINVAL;
-    // the plan image: head, jobs, items (counters and partials are device-only)
-    std::vector<unsigned char> img(hp.lay.counters, 0);
-    BatchHead hd;
-    memset(&hd, 0, sizeof(hd));
-    hd.nitems = (int)hp.items.size();
-    hd.njobs = njobs;
-    hd.ncounters = (int)hp.ncounters;
-    hd.off_jobs = (long long)hp.lay.jobs;
-    hd.off_items = (long long)hp.lay.items;
-    hd.off_counters = (long long)hp.lay.counters;
-    hd.off_spill = (long long)hp.lay.spill;
-    hd.off_partials = (long long)hp.lay.partials;
-    hd.zero_words = (long long)((hp.lay.partials - hp.lay.counters) / 8);
-    memcpy(img.data(), &hd, sizeof(hd));
-    if (njobs) memcpy(img.data() + hp.lay.jobs, hp.jobs.data(), hp.jobs.size() * sizeof(BatchJob));
-    if (!hp.items.empty()) memcpy(img.data() + hp.lay.items, hp.items.data(), hp.items.size() * sizeof(BatchItem));
+    size_t total = 0, image = 0;
+    if (!repro::batchx::plan_sizes(jobs, njobs, kt, vt, T, cfg, &total, &image)) return REPRO_EINVAL;
+    std::vector<unsigned char> img(image);
+    int rc = repro::batchx::plan_into(jobs, njobs, kt, vt, T, cfg, img.data(), img.size(), workspace, workspace_bytes,
+                                      plan);
+    if (rc != REPRO_OK) return rc;
     if (hipMemcpyAsync(workspace, img.data(), img.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
         return REPRO_EHIP;
     if (hipStreamSynchronize(stream) != hipSuccess) return REPRO_EHIP;
-    // dynamic LDS beyond 64 KiB must be allowed per kernel; done here, outside
-    // any graph capture of the launches
-    if (hp.lds > 64 * 1024 && hipFuncSetAttribute(pick_kernel(kt, vt, T), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                  (int)hp.lds) != hipSuccess)
-        return REPRO_EHIP;
-    memset(plan, 0, sizeof(*plan));
-    plan->workspace = workspace;
-    plan->items = (int64_t)hp.items.size();
-    plan->grid = (int)std::min<int64_t>(BATCH_MAX_WG, std::max<int64_t>(1, plan->items));
-    plan->lds_bytes = (int)hp.lds;
-    plan->kt = kt;
-    plan->vt = vt;
-    plan->T = T;
     return REPRO_OK;
 }
 

@@ -26,10 +26,13 @@
 #include <vector>
 
 #include "repro.h"
+#include "repro_batch_internal.hpp"
 
 namespace {
 
 constexpr int64_t SERVE_DEFAULT_CHUNK = 16ll << 20;
+constexpr int64_t SERVE_BATCH_CHUNK = 512 * 1024;  // rows per batch item (the tuned size on the batch workload)
+constexpr size_t SERVE_IMAGE_BYTES = 64 * 1024;    // pinned plan image per slot
 constexpr size_t SERVE_ALIGN = 256;
 
 inline size_t up(size_t x) { return (x + SERVE_ALIGN - 1) / SERVE_ALIGN * SERVE_ALIGN; }
@@ -85,10 +88,28 @@ class Arena {
 
 // Arena layout of one admitted query.
 struct QueryLayout {
-    size_t state_bytes, ws_bytes, total;
+    size_t state_bytes, ws_bytes, total, image_bytes;
     size_t off_state[REPRO_MAX_AGGS], off_prod[REPRO_MAX_AGGS], off_ws;
     int64_t chunk;
+    bool batch;  // aggregates as jobs of one batch launch
 };
+
+// The batch jobs of a query's aggregates; `prod` gives the product columns
+// (arena addresses, or stand-ins while only sizing).
+void query_jobs(const repro_query* q, void* const* states, const double* const* prod, repro_batch_job* jobs) {
+    for (int a = 0; a < q->naggs; ++a) {
+        repro_batch_job& j = jobs[a];
+        memset(&j, 0, sizeof(j));
+        j.keys = q->keys;
+        j.values = q->agg_b[a] >= 0 ? (const void*)prod[a] : (const void*)q->cols[q->agg_a[a]];
+        j.n = q->n;
+        j.num_groups = q->num_groups;
+        j.L = q->L;
+        j.accumulate = 0;
+        j.states = states[a];
+        j.out = q->out[a];
+    }
+}
 
 bool valid_query(const repro_query* q) {
     if (!q || q->n < 0 || q->num_groups < 1 || q->num_groups > INT32_MAX || q->L < 1 || q->L > 4 || q->naggs < 1 ||
@@ -103,15 +124,36 @@ bool valid_query(const repro_query* q) {
     return true;
 }
 
-bool layout_query(const repro_query* q, int64_t chunk_cfg, QueryLayout* ly) {
+bool layout_query(const repro_query* q, int64_t chunk_cfg, bool batch_path, QueryLayout* ly) {
     if (!valid_query(q)) return false;
     memset(ly, 0, sizeof(*ly));
     ly->chunk = chunk_cfg > 0 ? chunk_cfg : SERVE_DEFAULT_CHUNK;
     ly->state_bytes = repro_state_bytes(q->num_groups, REPRO_F64, q->L);
-    ly->ws_bytes = q->n > 0 ? repro_workspace_bytes(std::min<int64_t>(q->n, ly->chunk), q->num_groups, REPRO_I32,
-                                                    REPRO_F64, REPRO_F64, q->L)
-                            : 0;
     if (ly->state_bytes == 0) return false;
+    ly->batch = false;
+    if (batch_path && q->n > 0 && q->num_groups <= repro::batchx::slice_limit(q->L)) {
+        // the aggregates as batch jobs, sized with stand-in addresses
+        repro_batch_job jobs[REPRO_MAX_AGGS];
+        void* st[REPRO_MAX_AGGS];
+        const double* pr[REPRO_MAX_AGGS];
+        for (int a = 0; a < q->naggs; ++a) {
+            st[a] = reinterpret_cast<void*>((uintptr_t)SERVE_ALIGN * (a + 1));
+            pr[a] = reinterpret_cast<const double*>((uintptr_t)SERVE_ALIGN * (a + 9));
+        }
+        query_jobs(q, st, pr, jobs);
+        const repro_batch_config cfg{SERVE_BATCH_CHUNK, 0, 0};
+        size_t wsb = 0, img = 0;
+        if (repro::batchx::plan_sizes(jobs, q->naggs, REPRO_I32, REPRO_F64, REPRO_F64, &cfg, &wsb, &img) &&
+            img <= SERVE_IMAGE_BYTES) {
+            ly->batch = true;
+            ly->ws_bytes = wsb;
+            ly->image_bytes = img;
+        }
+    }
+    if (!ly->batch)
+        ly->ws_bytes = q->n > 0 ? repro_workspace_bytes(std::min<int64_t>(q->n, ly->chunk), q->num_groups, REPRO_I32,
+                                                        REPRO_F64, REPRO_F64, q->L)
+                                : 0;
     size_t off = 0;
     for (int a = 0; a < q->naggs; ++a) {
         ly->off_state[a] = off;
@@ -135,6 +177,7 @@ struct Pending {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    void* image = nullptr;  // pinned host memory: the batch plan of the slot's query
     bool busy = false;
     int64_t ticket = -1;
     size_t off = 0, bytes = 0;
@@ -150,6 +193,8 @@ struct repro_server {
     unsigned char* arena = nullptr;
     size_t arena_bytes = 0;
     int64_t chunk = SERVE_DEFAULT_CHUNK;
+    bool batch_path = true;
+    int query_wg = 0;
     Arena alloc;
     std::vector<Slot> slots;
     std::deque<Pending> queue;
@@ -165,7 +210,8 @@ int enqueue_query(repro_server* s, Slot& sl, const repro_query& q, const QueryLa
     const int64_t G = q.num_groups;
     const double* vals[REPRO_MAX_AGGS];
     for (int a = 0; a < q.naggs; ++a) {
-        if (repro_state_init(base + ly.off_state[a], G, REPRO_F64, q.L, st) != REPRO_OK) return REPRO_EHIP;
+        if (!ly.batch && repro_state_init(base + ly.off_state[a], G, REPRO_F64, q.L, st) != REPRO_OK)
+            return REPRO_EHIP;
         vals[a] = q.cols[q.agg_a[a]];
         if (q.agg_b[a] >= 0 && q.n > 0) {
             double* prod = reinterpret_cast<double*>(base + ly.off_prod[a]);
@@ -175,6 +221,23 @@ int enqueue_query(repro_server* s, Slot& sl, const repro_query& q, const QueryLa
             if (hipGetLastError() != hipSuccess) return REPRO_EHIP;
             vals[a] = prod;
         }
+    }
+    if (ly.batch) {
+        // one batch launch: a job per aggregate, states overwritten, sums finalised
+        repro_batch_job jobs[REPRO_MAX_AGGS];
+        void* states[REPRO_MAX_AGGS];
+        for (int a = 0; a < q.naggs; ++a) states[a] = base + ly.off_state[a];
+        query_jobs(&q, states, vals, jobs);
+        const repro_batch_config cfg{SERVE_BATCH_CHUNK, 0, 0};
+        repro_batch_plan plan;
+        int rc = repro::batchx::plan_into(jobs, q.naggs, REPRO_I32, REPRO_F64, REPRO_F64, &cfg, sl.image,
+                                          SERVE_IMAGE_BYTES, base + ly.off_ws, ly.ws_bytes, &plan);
+        if (rc != REPRO_OK) return rc;
+        if (s->query_wg > 0 && plan.grid > s->query_wg) plan.grid = s->query_wg;  // share the CUs between slots
+        if (hipMemcpyAsync(base + ly.off_ws, sl.image, ly.image_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+            return REPRO_EHIP;
+        if ((rc = repro::batchx::launch(&plan, q.status, st)) != REPRO_OK) return rc;
+        return hipEventRecord(sl.done, st) == hipSuccess ? REPRO_OK : REPRO_EHIP;
     }
     for (int64_t r0 = 0; r0 < q.n; r0 += ly.chunk) {
         const int64_t m = std::min<int64_t>(ly.chunk, q.n - r0);
@@ -196,7 +259,7 @@ extern "C" {
 
 size_t repro_query_bytes(const repro_query* q, const repro_server_config* cfg) {
     QueryLayout ly;
-    if (!layout_query(q, cfg ? cfg->chunk_rows : 0, &ly)) return 0;
+    if (!layout_query(q, cfg ? cfg->chunk_rows : 0, !(cfg && cfg->no_batch_path), &ly)) return 0;
     return ly.total;
 }
 
@@ -205,16 +268,19 @@ double repro_server_clock(void) { return now_s(); }
 int repro_server_create(void* arena, size_t arena_bytes, const repro_server_config* cfg, repro_server** srv) {
     if (!srv || !arena || (uintptr_t)arena % SERVE_ALIGN != 0 || arena_bytes < SERVE_ALIGN) return REPRO_EINVAL;
     const int nslots = cfg ? cfg->slots : 4;
-    if (nslots < 1 || nslots > 64 || (cfg && cfg->chunk_rows < 0)) return REPRO_EINVAL;
+    if (nslots < 1 || nslots > 64 || (cfg && (cfg->chunk_rows < 0 || cfg->query_workgroups < 0))) return REPRO_EINVAL;
     repro_server* s = new repro_server();
     s->arena = static_cast<unsigned char*>(arena);
     s->arena_bytes = arena_bytes / SERVE_ALIGN * SERVE_ALIGN;
     s->chunk = (cfg && cfg->chunk_rows > 0) ? cfg->chunk_rows : SERVE_DEFAULT_CHUNK;
+    s->batch_path = !(cfg && cfg->no_batch_path);
+    s->query_wg = cfg ? cfg->query_workgroups : 0;
     s->alloc.init(s->arena_bytes);
     s->slots.resize(nslots);
     for (Slot& sl : s->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc(&sl.image, SERVE_IMAGE_BYTES, hipHostMallocDefault) != hipSuccess) {
             repro_server_destroy(s);
             return REPRO_EHIP;
         }
@@ -226,7 +292,7 @@ int repro_server_create(void* arena, size_t arena_bytes, const repro_server_conf
 int repro_server_submit(repro_server* s, const repro_query* q, int64_t* ticket) {
     if (!s) return REPRO_EINVAL;
     QueryLayout ly;
-    if (!layout_query(q, s->chunk, &ly) || up(ly.total) > s->arena_bytes) return REPRO_EINVAL;
+    if (!layout_query(q, s->chunk, s->batch_path, &ly) || up(ly.total) > s->arena_bytes) return REPRO_EINVAL;
     Pending p;
     p.ticket = s->next_ticket++;
     p.q = *q;
@@ -266,7 +332,7 @@ int repro_server_poll(repro_server* s, int64_t* tickets, double* times, int cap,
         if (!free_slot) break;
         const Pending& p = s->queue.front();
         QueryLayout ly;
-        if (!layout_query(&p.q, s->chunk, &ly)) return REPRO_EINVAL;
+        if (!layout_query(&p.q, s->chunk, s->batch_path, &ly)) return REPRO_EINVAL;
         size_t off = 0;
         if (!s->alloc.alloc(ly.total, &off)) break;  // wait for memory
         free_slot->busy = true;
@@ -305,6 +371,7 @@ int repro_server_destroy(repro_server* s) {
             (void)hipStreamDestroy(sl.stream);
         }
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.image) (void)hipHostFree(sl.image);
     }
     delete s;
     return rc;

@@ -50,8 +50,9 @@ def oracle_sums(pool, keys, off, n, G, L=2):
     return outs
 
 
-def run_server(specs, arrival_gaps=None, slots=4, arena_bytes=4 << 30, chunk_rows=300_000, timeout=120.0):
-    srv = api.Server(arena_bytes, slots=slots, chunk_rows=chunk_rows)
+def run_server(specs, arrival_gaps=None, slots=4, arena_bytes=4 << 30, chunk_rows=300_000, timeout=120.0,
+               batch_path=True):
+    srv = api.Server(arena_bytes, slots=slots, chunk_rows=chunk_rows, batch_path=batch_path)
     try:
         t0 = srv.clock()
         arr = t0 + (np.cumsum(arrival_gaps) if arrival_gaps is not None else np.zeros(len(specs)))
@@ -72,18 +73,21 @@ def run_server(specs, arrival_gaps=None, slots=4, arena_bytes=4 << 30, chunk_row
         srv.close()
 
 
-def test_each_result_same_alone_and_in_the_mix():
+@pytest.mark.parametrize("batch_path", [True, False])
+def test_each_result_same_alone_and_in_the_mix(batch_path):
+    """Alone uses the other execution path for queries that fit LDS (one
+    batch launch vs chunked repro_groupby_sum), so the paths are compared too."""
     pool, host, specs, gaps = make_queries(14, max_rows=1_500_000, max_groups=1 << 20, salt=1)
     say(f"case serve mix: {len(specs)} queries, rows {[h[2] for h in host]}, groups {[h[3] for h in host]}")
     alone = []
     for s in specs:
-        run_server([s], slots=1)
+        run_server([s], slots=1, batch_path=not batch_path)
         alone.append([o.clone() for o in s.out])
     for s in specs:
         for o in s.out:
             o.fill_(float("nan"))
     # in the mix: arrivals 50 us apart on average, 4 slots, chunked states
-    lat, peak = run_server(specs, arrival_gaps=gaps * 50e-6, slots=4)
+    lat, peak = run_server(specs, arrival_gaps=gaps * 50e-6, slots=4, batch_path=batch_path)
     say(f"mix: peak running {peak}, latencies ms {np.round(np.array(lat) * 1e3, 2)}")
     assert peak >= 2, "queries should have overlapped"
     for q, (s, a, (keys, off, n, G)) in enumerate(zip(specs, alone, host)):
