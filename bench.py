@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_agg_lds_lowcard_200M_g1024_L3_pmc.md")
 # the sources that define the low-cardinality aggregation kernel, hashed in this order
-KERNEL_SOURCES = ("repro.hip", "repro_agg.hpp", "repro_device.hpp")
+KERNEL_SOURCES = ("repro_cols.hip", "repro_lds.hpp", "repro_agg.hpp", "repro_device.hpp")
 
 
 def measured_traffic():
@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--config", choices=sorted(CONFIGS), default="lowcard")
     ap.add_argument("--rows", type=int, default=0, help="override the config's row count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--per-column", action="store_true",
+                    help="aggregate the columns of a multi-column workload in separate calls (one key pass each)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (HBM counter calibration)")
@@ -137,20 +139,32 @@ def main():
     ws = torch.empty(max(wsb, 256), dtype=torch.uint8, device=dev)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
 
+    fused = len(vts) > 1 and not args.per_column
+    if fused:
+        wsb = max(wsb, api.workspace_bytes_cols(n, G, kt.dtype, [v.dtype for _, v in vts], L, T))
+        ws = torch.empty(max(wsb, 256), dtype=torch.uint8, device=dev)
+
     def step():
         for st in states:
             api.state_reset(st, G, L, T)
-        for st, (_, v) in zip(states, vts):
-            api.groupby_sum(kt, v, G, L, T, states=st, status=status, workspace=ws)
+        if fused:  # one key pass for every column
+            api.groupby_sum_cols(kt, [v for _, v in vts], G, L, T, states=states, status=status, workspace=ws)
+        else:
+            for st, (_, v) in zip(states, vts):
+                api.groupby_sum(kt, v, G, L, T, states=st, status=status, workspace=ws)
         for st, out in zip(states, outs):
             api.finalize(st, G, L, T, out=out)
 
     plains = [torch.zeros(G, dtype=torch.float64, device=dev) for _ in vts]
 
     def plain_step():
-        for pl, (_, v) in zip(plains, vts):
+        for pl in plains:
             pl.zero_()
-            api.plain_groupby_sum(kt, v, G, out=pl)
+        if fused:
+            api.plain_groupby_sum_cols(kt, [v for _, v in vts], G, outs=plains)
+        else:
+            for pl, (_, v) in zip(plains, vts):
+                api.plain_groupby_sum(kt, v, G, out=pl)
 
     log(f"warmup {args.warmup} steps")
     for _ in range(args.warmup):
@@ -160,7 +174,7 @@ def main():
         raise SystemExit(f"device status {int(status.item())} on a clean workload")
 
     log(f"timing {args.steps} steps")
-    ncol = len(vts)
+    ncol = 1 if fused else len(vts)  # aggregation launches per step
     api.profile_arm(ncol * args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -171,8 +185,9 @@ def main():
     kms = api.profile_read()
     ms_step = (t1 - t0) * 1000.0 / args.steps
     kcol = [kms[i::ncol] for i in range(ncol)]
+    knames = ["+".join(name for name, _ in vts)] if fused else [name for name, _ in vts]
     log(f"step {ms_step:.3f} ms; aggregation kernel " +
-        ", ".join(f"{name} {np.mean(k):.3f} ms" for (name, _), k in zip(vts, kcol)))
+        ", ".join(f"{name} {np.mean(k):.3f} ms" for name, k in zip(knames, kcol)))
 
     # inputs small enough to stay in the 256 MB Infinity Cache between steps:
     # also time single steps after streaming 1 GiB through the caches (cold)
@@ -207,8 +222,13 @@ def main():
     # algorithmic bytes: rows read once per column; states and outputs written once
     kb = keys.dtype.itemsize
     state_b = api.state_bytes(G, L, T)
-    alg_step = sum(n * (kb + v.element_size()) + state_b + G * 8 for _, v in vts)
-    alg_k0 = n * (kb + vts[0][1].element_size())
+    vsum = sum(v.element_size() for _, v in vts)
+    if fused:  # the keys are read once for all columns
+        alg_step = n * (kb + vsum) + len(vts) * (state_b + G * 8)
+        alg_k0 = n * (kb + vsum)
+    else:
+        alg_step = sum(n * (kb + v.element_size()) + state_b + G * 8 for _, v in vts)
+        alg_k0 = n * (kb + vts[0][1].element_size())
     k0 = float(np.mean(kcol[0]))
     ach_gbs = alg_k0 / (k0 * 1e-3) / 1e9
     kname = {"lowcard": "k_agg_lds<int32,f64,f64,L=3>", "plain": "k_agg_lds<int32,f64,f64,L=2>",
@@ -216,8 +236,10 @@ def main():
              "highcard": "k_agg_part<f64,f64,L=2> (after partitioning)"}[args.config]
     roofline = {"bound": "hbm", "achieved": round(ach_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach_gbs / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic() if args.config == "lowcard" and n == CONFIGS["lowcard"]["rows"] else None,
-                "kernel": f"{kname} ({vts[0][0]} column)", "kernel_ms": round(k0, 4),
+                "traffic": measured_traffic() if fused and n == CONFIGS["lowcard"]["rows"] else None,
+                "kernel": (f"k_agg_cols<int32,L={L},NC={len(vts)}> ({' + '.join(nm for nm, _ in vts)} columns, one "
+                           f"key pass)") if fused else f"{kname} ({vts[0][0]} column)",
+                "kernel_ms": round(k0, 4),
                 "alg_bytes_per_launch": alg_k0}
     if args.config == "highcard":
         # the dominant cost is the whole partitioned pass: report it against the
@@ -243,7 +265,8 @@ def main():
         "dtype": "f32" if args.config == "float" else "f64",
         "data": "synthetic",
         "config": {"workload": cfg["desc"].format(n=n, G=G, L=L), "name": args.config, "rows": n, "groups": G,
-                   "L": L, "columns": [name for name, _ in vts], "parallelism": "single GPU"},
+                   "L": L, "columns": [name for name, _ in vts], "key_passes": 1 if fused else len(vts),
+                   "parallelism": "single GPU"},
         "step_hbm_frac": round(alg_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "cold_cache_ms_per_step": round(cold_ms, 4) if cold_ms is not None else None,
         "plain_fp64_atomic": {"ms_per_step": round(plain_ms, 4), "slowdown": round(ms_step / plain_ms, 3)},

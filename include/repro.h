@@ -65,6 +65,9 @@ enum {
 typedef enum { REPRO_F32 = 0, REPRO_F64 = 1 } repro_scalar_t;
 typedef enum { REPRO_I32 = 0, REPRO_I64 = 1 } repro_key_t;
 
+/* value columns of one multi-column call or served query, at most */
+#define REPRO_MAX_COLS 8
+
 /*
  * Bytes of a state buffer for G groups (layout above).  Returns 0 for
  * invalid arguments (G < 1, L outside 1..4).
@@ -132,6 +135,42 @@ int repro_finalize(const void* states, int64_t num_groups, repro_scalar_t T, int
  */
 int repro_plain_groupby_sum(const void* keys, repro_key_t kt, const void* values, repro_scalar_t vt, int64_t n,
                             int64_t num_groups, double* out, uint32_t* status, hipStream_t stream);
+
+/*
+ * Several SUM aggregates over one GROUP BY (Sec. V-D: a query's aggregates
+ * per group; Sec. VI-E's TPC-H Q1 has several SUMs over one key): for every
+ * column c = 0..ncols-1, states[c] += the GroupBy-SUM of values[c] over
+ * keys, with exactly the bits repro_groupby_sum gives for that column
+ * alone.  The key column is read once for up to four columns whose groups
+ * fit one workgroup's LDS together (T = double); other shapes run column by
+ * column.
+ *
+ *   ncols      1 .. REPRO_MAX_COLS.
+ *   values     HOST array of ncols device pointers, each n entries of type
+ *              vts[c] (HOST array).  Fusion needs keys aligned to two keys
+ *              and each column to two of its elements; otherwise the call
+ *              still works, column by column.
+ *   states     HOST array of ncols distinct device state buffers.
+ *   workspace  >= repro_workspace_bytes_cols(...) bytes, 256-byte aligned.
+ *   other arguments and errors as for repro_groupby_sum; REPRO_EINVAL is
+ *   returned before anything is enqueued.
+ */
+size_t repro_workspace_bytes_cols(int64_t n, int64_t num_groups, repro_key_t kt, int ncols,
+                                  const repro_scalar_t* vts, repro_scalar_t T, int L);
+int repro_groupby_sum_cols(const void* keys, repro_key_t kt, int ncols, const void* const* values,
+                           const repro_scalar_t* vts, int64_t n, int64_t num_groups, repro_scalar_t T, int L,
+                           void* const* states, void* workspace, size_t workspace_bytes, uint32_t* status,
+                           hipStream_t stream);
+
+/*
+ * Baseline of the multi-column call, NOT reproducible: outs[c][g] +=
+ * values[c][i] for keys[i] == g with plain double atomics, the key column
+ * read once for up to four columns.  outs is a HOST array of ncols device
+ * double[num_groups] buffers, accumulated into.
+ */
+int repro_plain_groupby_sum_cols(const void* keys, repro_key_t kt, int ncols, const void* const* values,
+                                 const repro_scalar_t* vts, int64_t n, int64_t num_groups, double* const* outs,
+                                 uint32_t* status, hipStream_t stream);
 
 /*
  * Ungrouped reproducible sum (RSum over a whole column, Sec. III-C/III-D):
@@ -263,7 +302,6 @@ int repro_batch_tune(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
  * execution path do not change a bit.  The server allocates pinned host
  * memory for plan uploads (a few KiB per slot), no device memory.
  */
-#define REPRO_MAX_COLS 8
 #define REPRO_MAX_AGGS 4
 
 typedef struct {

@@ -116,6 +116,12 @@ def load():
     lib.repro_server_clock.argtypes = []
     lib.repro_server_destroy.restype = ctypes.c_int
     lib.repro_server_destroy.argtypes = [vp]
+    lib.repro_workspace_bytes_cols.restype = sz
+    lib.repro_workspace_bytes_cols.argtypes = [i64, i64, i32, i32, vp, i32, i32]
+    lib.repro_groupby_sum_cols.restype = ctypes.c_int
+    lib.repro_groupby_sum_cols.argtypes = [vp, i32, i32, vp, vp, i64, i64, i32, i32, vp, vp, sz, vp, vp]
+    lib.repro_plain_groupby_sum_cols.restype = ctypes.c_int
+    lib.repro_plain_groupby_sum_cols.argtypes = [vp, i32, i32, vp, vp, i64, i64, vp, vp, vp]
     lib.repro_version.restype = ctypes.c_char_p
     lib.repro_version.argtypes = []
     for name in ("repro_state_init", "repro_groupby_sum", "repro_merge", "repro_finalize",

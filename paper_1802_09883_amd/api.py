@@ -104,6 +104,69 @@ def groupby_sum(keys: torch.Tensor, values: torch.Tensor, num_groups: int, L: in
     return states
 
 
+def workspace_bytes_cols(n: int, num_groups: int, key_dtype, value_dtypes, L: int = 2, T=torch.float64) -> int:
+    vts = (ctypes.c_int * len(value_dtypes))(*[_SCALAR[d] for d in value_dtypes])
+    return int(_lib.load().repro_workspace_bytes_cols(n, num_groups, _KEY[key_dtype], len(value_dtypes), vts,
+                                                      _T(T), L))
+
+
+def _check_cols(keys, columns):
+    if keys.dtype not in _KEY or keys.dim() != 1 or not keys.is_cuda:
+        raise TypeError("keys must be a 1-D int32/int64 GPU tensor")
+    if not 1 <= len(columns) <= _lib.MAX_COLS:
+        raise ValueError(f"1..{_lib.MAX_COLS} value columns")
+    for v in columns:
+        if v.dtype not in _SCALAR or v.shape != keys.shape or v.device != keys.device:
+            raise ValueError("value columns must be float32/float64 of the keys' shape, on the keys' GPU")
+
+
+def groupby_sum_cols(keys: torch.Tensor, columns, num_groups: int, L: int = 2, T=torch.float64, states=None,
+                     status: torch.Tensor | None = None, workspace: torch.Tensor | None = None, stream=None):
+    """Several SUM aggregates over one GROUP BY: states[c] += the GroupBy-SUM
+    of columns[c] (one key pass for up to four columns).  Returns the list of
+    states (fresh ones where none are given); each has the bits
+    ``groupby_sum`` gives for its column alone."""
+    lib = _lib.load()
+    _check_cols(keys, columns)
+    keys = keys.contiguous()
+    columns = [v.contiguous() for v in columns]
+    dev = keys.device
+    if states is None:
+        states = [state_init(num_groups, L, T, dev, stream) for _ in columns]
+    if len(states) != len(columns):
+        raise ValueError("one state per column")
+    n = keys.numel()
+    need = workspace_bytes_cols(n, num_groups, keys.dtype, [v.dtype for v in columns], L, T)
+    ws = workspace if workspace is not None else (_workspace(need, dev, stream) if need else None)
+    nc = len(columns)
+    vals = (ctypes.c_void_p * nc)(*[v.data_ptr() for v in columns])
+    vts = (ctypes.c_int * nc)(*[_SCALAR[v.dtype] for v in columns])
+    sts = (ctypes.c_void_p * nc)(*[s.data_ptr() for s in states])
+    rc = lib.repro_groupby_sum_cols(_vp(keys), _KEY[keys.dtype], nc, vals, vts, n, num_groups, _T(T), L, sts,
+                                    _vp(ws), ws.numel() if ws is not None else 0, _vp(status), _stream(dev, stream))
+    _lib.check(rc, "groupby_sum_cols")
+    return states
+
+
+def plain_groupby_sum_cols(keys: torch.Tensor, columns, num_groups: int, outs=None, status=None, stream=None):
+    """Non-reproducible baseline over several columns (plain double atomics,
+    one key pass for up to four columns); outs are accumulated into."""
+    lib = _lib.load()
+    _check_cols(keys, columns)
+    keys = keys.contiguous()
+    columns = [v.contiguous() for v in columns]
+    if outs is None:
+        outs = [torch.zeros(num_groups, dtype=torch.float64, device=keys.device) for _ in columns]
+    nc = len(columns)
+    vals = (ctypes.c_void_p * nc)(*[v.data_ptr() for v in columns])
+    vts = (ctypes.c_int * nc)(*[_SCALAR[v.dtype] for v in columns])
+    ops = (ctypes.c_void_p * nc)(*[o.data_ptr() for o in outs])
+    rc = lib.repro_plain_groupby_sum_cols(_vp(keys), _KEY[keys.dtype], nc, vals, vts, keys.numel(), num_groups, ops,
+                                          _vp(status), _stream(keys.device, stream))
+    _lib.check(rc, "plain_groupby_sum_cols")
+    return outs
+
+
 def sum(values: torch.Tensor, L: int = 2, T=torch.float64, state: torch.Tensor | None = None,
         status: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Ungrouped reproducible sum of a column into a one-group state

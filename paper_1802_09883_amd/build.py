@@ -13,7 +13,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("repro.hip", "repro_sum.hip", "repro_batch.hip", "repro_serve.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("repro.hip", "repro_cols.hip", "repro_sum.hip", "repro_batch.hip", "repro_serve.hip")]
 OUT = os.path.join(HERE, "librepro.so")
 
 HIPCC_FLAGS = [

@@ -26,8 +26,31 @@
 #include "repro.h"
 #include "repro_device.hpp"
 #include "repro_agg.hpp"
+#include "repro_lds.hpp"
 
 using namespace repro;
+
+namespace repro {
+namespace {
+// ------------------------------------------------------------ profiling
+constexpr int PROFILE_MAX = 4096;
+struct ProfileSlot {
+    hipEvent_t ev[2 * PROFILE_MAX];
+    int created = 0, armed = 0, used = 0;
+};
+thread_local ProfileSlot* g_prof = nullptr;
+
+}  // namespace
+
+void prof_before(hipStream_t st) {
+    if (g_prof && g_prof->used < g_prof->armed) (void)hipEventRecord(g_prof->ev[2 * g_prof->used], st);
+}
+void prof_after(hipStream_t st) {
+    if (g_prof && g_prof->used < g_prof->armed) (void)hipEventRecord(g_prof->ev[2 * g_prof->used++ + 1], st);
+}
+
+
+}  // namespace repro
 
 namespace {
 
@@ -58,10 +81,6 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_lds(const KT* __restrict__ ke
     report(status, err);
 }
 
-// Zeroes the spill array before an aggregation pass.
-__global__ void __launch_bounds__(256) k_zero(unsigned long long* __restrict__ p, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = 0;
-}
 
 // ------------------------------------------------- high cardinality path
 //
@@ -426,157 +445,6 @@ __global__ void __launch_bounds__(256) k_merge_part(const WorkItem* __restrict__
     }
 }
 
-// ------------------------------------------------------------- merging
-//
-// The workgroup partials (top, K[L]) of every group are folded into the
-// caller's canonical state in two launches (operator+=(repro) over all
-// partials).  Every step is exact integer arithmetic, so the split into
-// blocks does not change any bit.
-//
-// Level 1 (k_merge_l1): block (x, y) takes groups x*64 .. x*64+63 (one per
-// lane) and partials y*PB .. y*PB+PB-1 (spread over the 4 waves).  It forms
-// their common top J (the largest), moves each partial's levels down by its
-// distance to J and adds the level sums split as hi = sum(K >> CARRY),
-// lo = sum(K & (2^CARRY - 1)) (no int64 overflow: |K| < 2^62 per partial).
-// Level 2 (k_merge_l2): one lane per group adds the level-1 results and the
-// caller's state the same way and writes the canonical (S, C).
-constexpr int M1_GROUPS = 64, M1_WAVES = 4;
-constexpr int M2_GROUPS = 16, M2_SLICES = 16;
-
-template <class AT, int L>
-__global__ void __launch_bounds__(M1_GROUPS* M1_WAVES)
-    k_merge_l1(const int* __restrict__ ptop, const long long* __restrict__ pK, int nparts, int PB, int G,
-               int* __restrict__ qtop, long long* __restrict__ qhi, long long* __restrict__ qlo) {
-    constexpr int c = Fmt<AT>::CARRY;
-    __shared__ int sJ[M1_WAVES][M1_GROUPS];
-    __shared__ long long sH[M1_WAVES][L][M1_GROUPS], sLo[M1_WAVES][L][M1_GROUPS];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = blockIdx.x * M1_GROUPS + lane;
-    const bool gv = g < G;
-    const int gg = gv ? g : 0;  // clamped: loads stay in bounds, results unused
-    const int p0 = blockIdx.y * PB;
-    const int p1 = min(nparts, p0 + PB);
-    int J = L - 1;
-    for (int p = p0 + wave; p < p1; p += M1_WAVES) J = max(J, ptop[(size_t)p * G + gg]);
-    sJ[wave][lane] = J;
-    __syncthreads();
-#pragma unroll
-    for (int w = 0; w < M1_WAVES; ++w) J = max(J, sJ[w][lane]);
-    long long hi[L], lo[L];
-#pragma unroll
-    for (int l = 0; l < L; ++l) hi[l] = lo[l] = 0;
-    for (int p = p0 + wave; p < p1; p += M1_WAVES) {
-        const int d = J - ptop[(size_t)p * G + gg];
-        long long x[L];
-#pragma unroll
-        for (int l = 0; l < L; ++l) x[l] = pK[((size_t)p * L + l) * G + gg];
-#pragma unroll
-        for (int l = 0; l < L; ++l) {
-            // level l of the result is level l - d of this partial
-            long long v = 0;
-#pragma unroll
-            for (int q = 0; q < L; ++q) v = (q == l - d) ? x[q] : v;
-            hi[l] += v >> c;
-            lo[l] += v & ((1ll << c) - 1);
-        }
-    }
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        sH[wave][l][lane] = hi[l];
-        sLo[wave][l][lane] = lo[l];
-    }
-    __syncthreads();
-    if (wave != 0 || !gv) return;
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        long long h = 0, o = 0;
-#pragma unroll
-        for (int w = 0; w < M1_WAVES; ++w) {
-            h += sH[w][l][lane];
-            o += sLo[w][l][lane];
-        }
-        qhi[((size_t)blockIdx.y * L + l) * G + g] = h;
-        qlo[((size_t)blockIdx.y * L + l) * G + g] = o;
-    }
-    qtop[(size_t)blockIdx.y * G + g] = J;
-}
-
-template <class AT, int L>
-__global__ void __launch_bounds__(M2_GROUPS* M2_SLICES)
-    k_merge_l2(const int* __restrict__ qtop, const long long* __restrict__ qhi, const long long* __restrict__ qlo,
-               int nq, int G, const unsigned long long* __restrict__ spill, AT* __restrict__ S,
-               long long* __restrict__ C) {
-    constexpr int NJ = Fmt<AT>::JMAX + 1;
-    typedef Fmt<AT> F;
-    __shared__ int sJ[M2_SLICES][M2_GROUPS];
-    __shared__ long long sH[M2_SLICES][L][M2_GROUPS], sLo[M2_SLICES][L][M2_GROUPS];
-    const int lane = threadIdx.x % M2_GROUPS, sl = threadIdx.x / M2_GROUPS;
-    const int g = blockIdx.x * M2_GROUPS + lane;
-    const bool gv = g < G;
-    const int gg = gv ? g : 0;
-    const int ts = state_top(S[gg]);
-    int J = ts;
-    for (int q = sl; q < nq; q += M2_SLICES) J = max(J, qtop[(size_t)q * G + gg]);
-    sJ[sl][lane] = J;
-    __syncthreads();
-#pragma unroll
-    for (int w = 0; w < M2_SLICES; ++w) J = max(J, sJ[w][lane]);
-    long long hi[L], lo[L];
-#pragma unroll
-    for (int l = 0; l < L; ++l) hi[l] = lo[l] = 0;
-    for (int q = sl; q < nq; q += M2_SLICES) {
-        const int d = J - qtop[(size_t)q * G + gg];
-        long long xh[L], xl[L];
-#pragma unroll
-        for (int l = 0; l < L; ++l) {
-            xh[l] = qhi[((size_t)q * L + l) * G + gg];
-            xl[l] = qlo[((size_t)q * L + l) * G + gg];
-        }
-#pragma unroll
-        for (int l = 0; l < L; ++l) {
-#pragma unroll
-            for (int r = 0; r < L; ++r) {
-                if (r == l - d) {
-                    hi[l] += xh[r];
-                    lo[l] += xl[r];
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        sH[sl][l][lane] = hi[l];
-        sLo[sl][l][lane] = lo[l];
-    }
-    __syncthreads();
-    if (sl != 0 || !gv) return;
-    const int ds = J - ts;
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        long long h = (l - ds >= 0) ? C[(size_t)(l - ds) * G + g] : 0;
-        long long o = (l - ds >= 0) ? state_lo(S[(size_t)(l - ds) * G + g]) : 0;
-#pragma unroll
-        for (int w = 0; w < M2_SLICES; ++w) {
-            h += sH[w][l][lane];
-            o += sLo[w][l][lane];
-        }
-        // spilled units at lattice index J - l: H * 2^64 + w
-        const unsigned long long* sw = spill + ((size_t)g * NJ + (J - l)) * 2;
-        const i128 T = (i128)(long long)sw[1] * ((i128)1 << 64) + (i128)sw[0];
-        h += (long long)(T >> Fmt<AT>::CARRY);
-        o += (long long)(T & ((1ll << Fmt<AT>::CARRY) - 1));
-        hi[l] = h;
-        lo[l] = o;
-    }
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        long long cc, oo;
-        normalise<AT>(hi[l], lo[l], &cc, &oo);
-        S[(size_t)l * G + g] = make_S((AT*)0, F::B + (J - l) * F::W, oo);
-        C[(size_t)l * G + g] = cc;
-    }
-}
-
 // operator+=(repro) on whole state arrays: dst[g] += src[g].
 template <class AT, int L>
 __global__ void __launch_bounds__(256) k_merge_states(AT* __restrict__ Sd, long long* __restrict__ Cd,
@@ -710,48 +578,6 @@ __global__ void __launch_bounds__(PLAIN_BLOCK) k_plain_global(const KT* __restri
 
 // ================================================================ host
 
-// ------------------------------------------------------------ profiling
-constexpr int PROFILE_MAX = 4096;
-struct ProfileSlot {
-    hipEvent_t ev[2 * PROFILE_MAX];
-    int created = 0, armed = 0, used = 0;
-};
-thread_local ProfileSlot* g_prof = nullptr;
-
-inline void prof_before(hipStream_t st) {
-    if (g_prof && g_prof->used < g_prof->armed) (void)hipEventRecord(g_prof->ev[2 * g_prof->used], st);
-}
-inline void prof_after(hipStream_t st) {
-    if (g_prof && g_prof->used < g_prof->armed) (void)hipEventRecord(g_prof->ev[2 * g_prof->used++ + 1], st);
-}
-
-// partials per level-1 block: enough blocks to fill the chip, at most 64
-inline int merge_pb(int nwg, int G) {
-    const int gx = (G + M1_GROUPS - 1) / M1_GROUPS;
-    int pb = 4;
-    while (pb < 64 && (int64_t)gx * ((nwg + pb - 1) / pb) > 1024) pb *= 2;
-    return pb;
-}
-
-struct Plan {
-    int path;       // 1: LDS bins over all groups, 2: partitioned
-    // path 2
-    int gp_shift, F, nw;     // groups per partition 2^gp_shift, partitions, hist/scatter workgroups
-    size_t lds_sc;           // scatter LDS
-    int sc_ru;               // scatter rows per thread and tile
-    int64_t chunk_hs;        // rows per hist/scatter workgroup
-    int maxw;                // work items, upper bound
-    size_t o_counts, o_rel, o_size, o_base, o_wfirst, o_items, o_nitems, o_lkey, o_lval, o_ptop, o_pK;
-    size_t lds_agg2;         // LDS of k_agg_part
-    int nwg;        // aggregate workgroups
-    int64_t chunk;  // rows per workgroup (multiple of the tile)
-    int R;          // LDS bin replicas
-    int pb, nq;     // partials per level-1 merge block, level-1 results
-    size_t spill_off, spill_words;  // spill array: G x (JMAX+1) x {w, H}
-    size_t lds;     // dynamic LDS bytes
-    size_t ws;      // workspace bytes
-};
-
 inline size_t scalar_size(repro_scalar_t t) { return t == REPRO_F64 ? 8 : 4; }
 
 bool valid_common(int64_t G, repro_scalar_t T, int L) {
@@ -798,66 +624,11 @@ bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
 }
 
 bool make_plan(int64_t n, int64_t G, int L, int jmax, size_t vsize, Plan* p) {
-    memset(p, 0, sizeof(*p));
-    const size_t lds1 = agg_lds_bytes(G, L, 1);
-    if (lds1 > LDS_BIN_BUDGET) return make_plan_part(n, G, L, vsize, p);
-    p->path = 1;
-    p->R = replicas_for(G, L);
-    p->lds = agg_lds_bytes(G, L, p->R);
-    int64_t nwg = (n + MIN_ROWS_PER_WG - 1) / MIN_ROWS_PER_WG;
-    if (nwg > MAX_AGG_WG) nwg = MAX_AGG_WG;
-    if (nwg < (n + MAX_ROWS_PER_WG - 1) / MAX_ROWS_PER_WG) nwg = (n + MAX_ROWS_PER_WG - 1) / MAX_ROWS_PER_WG;
-    if (nwg < 1) nwg = 1;
-    int64_t chunk = (n + nwg - 1) / nwg;
-    chunk = (chunk + AGG_TILE - 1) / AGG_TILE * AGG_TILE;
-    if (chunk < AGG_TILE) chunk = AGG_TILE;
-    nwg = (n + chunk - 1) / chunk;
-    if (nwg < 1) nwg = 1;
-    if (nwg > 4096) return false;  // keeps the merge's int64 carry sums exact
-    p->nwg = (int)nwg;
-    p->chunk = chunk;
-    p->pb = merge_pb(p->nwg, (int)G);
-    p->nq = (p->nwg + p->pb - 1) / p->pb;
-    size_t ws = 0;
-    ws += align_up((size_t)nwg * G * 4, 256);          // partial tops
-    ws += align_up((size_t)nwg * G * L * 8, 256);      // partial K
-    ws += align_up((size_t)p->nq * G * 4, 256);        // level-1 tops
-    ws += 2 * align_up((size_t)p->nq * G * L * 8, 256);  // level-1 hi, lo
-    p->spill_off = ws;
-    p->spill_words = (size_t)G * (jmax + 1) * 2;
-    ws += align_up(p->spill_words * 8, 256);
-    p->ws = ws;
-    return true;
-}
-
-#define LAUNCH_CHECK()                                  \
-    do {                                                \
-        if (hipGetLastError() != hipSuccess) return REPRO_EHIP; \
-    } while (0)
-
-template <class AT, int L>
-int run_merge(const Plan& p, int G, unsigned char* ws, AT* S, long long* C, hipStream_t st) {
-    int* ptop = reinterpret_cast<int*>(ws);
-    long long* pK = reinterpret_cast<long long*>(ws + align_up((size_t)p.nwg * G * 4, 256));
-    unsigned char* q = reinterpret_cast<unsigned char*>(pK) + align_up((size_t)p.nwg * G * L * 8, 256);
-    int* qtop = reinterpret_cast<int*>(q);
-    long long* qhi = reinterpret_cast<long long*>(q + align_up((size_t)p.nq * G * 4, 256));
-    long long* qlo = reinterpret_cast<long long*>(reinterpret_cast<unsigned char*>(qhi) +
-                                                  align_up((size_t)p.nq * G * L * 8, 256));
-    hipLaunchKernelGGL((k_merge_l1<AT, L>), dim3((G + M1_GROUPS - 1) / M1_GROUPS, p.nq), dim3(M1_GROUPS * M1_WAVES),
-                       0, st, ptop, pK, p.nwg, p.pb, G, qtop, qhi, qlo);
-    LAUNCH_CHECK();
-    const unsigned long long* spill = reinterpret_cast<const unsigned long long*>(ws + p.spill_off);
-    hipLaunchKernelGGL((k_merge_l2<AT, L>), dim3((G + M2_GROUPS - 1) / M2_GROUPS), dim3(M2_GROUPS * M2_SLICES), 0,
-                       st, qtop, qhi, qlo, p.nq, G, spill, S, C);
-    LAUNCH_CHECK();
-    return REPRO_OK;
-}
-
-// Dynamic LDS beyond 64 KiB must be allowed per kernel on gfx950.
-inline bool allow_lds(const void* fn, size_t bytes) {
-    if (bytes <= 64 * 1024) return true;
-    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+    if (agg_lds_bytes(G, L, 1) > LDS_BIN_BUDGET) {
+        memset(p, 0, sizeof(*p));
+        return make_plan_part(n, G, L, vsize, p);
+    }
+    return make_plan_lds(n, G, L, jmax, AGG_TILE, p);
 }
 
 template <class KT, class VT, class AT, int L>
@@ -940,10 +711,10 @@ int run_groupby(const void* keys, const void* values, int64_t n, int64_t G64, vo
                            p.chunk, ptop, pK, spill, status);
     LAUNCH_CHECK();
     prof_after(st);
-    AT* S = static_cast<AT*>(states);
-    long long* C = reinterpret_cast<long long*>(static_cast<unsigned char*>(states) +
-                                                align_up((size_t)G * L * sizeof(AT), 8));
-    return run_merge<AT, L>(p, G, ws, S, C, st);
+    ColStates<AT> cs;
+    cs.S[0] = static_cast<AT*>(states);
+    cs.C[0] = reinterpret_cast<long long*>(static_cast<unsigned char*>(states) + align_up((size_t)G * L * sizeof(AT), 8));
+    return run_merge<AT, L>(p, G, 1, ws, cs, st);
 }
 
 template <class KT, class VT, class AT>

@@ -23,7 +23,9 @@ constexpr int ROWS_PER_THREAD = 8;
 constexpr int PREFETCH = 1;  // tiles loaded ahead of the one being processed
 constexpr int AGG_TILE = AGG_BLOCK * ROWS_PER_THREAD;
 constexpr int MAX_AGG_WG = 256;
-constexpr int64_t MIN_ROWS_PER_WG = 4 * (int64_t)AGG_TILE;
+// Small inputs spread over many workgroups of one tile each (load latency,
+// not bandwidth, bounds them); the partials they add are few at such sizes.
+constexpr int64_t MIN_ROWS_PER_WG = (int64_t)AGG_TILE;
 // A bin word takes at most (rows of one workgroup) units of magnitude
 // <= 2^(W-1) <= 2^39; 2^23 rows keep it below 2^62.
 constexpr int64_t MAX_ROWS_PER_WG = (int64_t)1 << 23;
@@ -212,17 +214,17 @@ __device__ __forceinline__ int frexp_raw(double v) { return __builtin_amdgcn_fre
 __device__ __forceinline__ int frexp_raw(float v) { return __builtin_amdgcn_frexp_expf(v); }
 
 // Per-row classification of a tile.  A row is deposited when its key is a
-// group id, its value finite, nonzero and inside the domain of AT; other
-// rows go to the trash slot G with required top 0.  `clean` stays true
+// group id and its value finite and zero or inside the domain of AT; other
+// rows go to the trash slot G.  Zeros require no top (j = 0).  `clean` stays true
 // while no row of this lane is an error (zero values are not errors).
 // With SLICE, the bins hold only groups [glo, glo + G) of Gfull groups: a
 // row whose key is a valid group outside the slice is skipped (no error);
 // deposited rows get bin index key - glo.
-template <bool FULL, bool SLICE, class KT, class VT, class AT>
+template <bool FULL, bool SLICE, class KT, class VT, class AT, int N = ROWS_PER_THREAD>
 __device__ __forceinline__ void classify_rows(const KT* kc, const VT* vc, uint32_t inr, int G, int* gi, int* ji,
                                               bool& clean, int64_t glo, int64_t Gfull) {
 #pragma unroll
-    for (int i = 0; i < ROWS_PER_THREAD; ++i) {
+    for (int i = 0; i < N; ++i) {
         const VT v = vc[i];
         const bool in = FULL || ((inr >> i) & 1u);
         const int64_t key = (int64_t)kc[i];
@@ -233,18 +235,19 @@ __device__ __forceinline__ void classify_rows(const KT* kc, const VT* vc, uint32
         const bool nz = v != (VT)0;
         const int j = jreq_raw<AT>(frexp_raw(v));
         const bool dom = j <= Fmt<AT>::JMAX;
-        const bool use = in && ins && fin && nz && dom;
+        // zeros keep their group (their units are zero) but raise no top
+        const bool use = in && ins && fin && (dom || !nz);
         clean = clean && (!in || (kok && fin && (dom || !nz)));
         gi[i] = use ? (int)(SLICE ? (uint32_t)key - (uint32_t)glo : (uint32_t)key) : G;
-        ji[i] = use ? j : 0;
+        ji[i] = (use && nz) ? j : 0;
     }
 }
 
 // Status bits of the error rows among this lane's rows (slow path).
-template <class KT, class VT, class AT>
+template <class KT, class VT, class AT, int N = ROWS_PER_THREAD>
 __device__ __forceinline__ uint32_t error_bits(const KT* kc, const VT* vc, uint32_t inr, int64_t G) {
     uint32_t e = 0;
-    for (int i = 0; i < ROWS_PER_THREAD; ++i) {
+    for (int i = 0; i < N; ++i) {
         if (!((inr >> i) & 1u)) continue;
         const VT v = vc[i];
         if ((uint64_t)(int64_t)kc[i] >= (uint64_t)G) e |= ERR_KEY;
@@ -280,6 +283,149 @@ __device__ __forceinline__ void spill_row(unsigned long long* __restrict__ spill
     for (int l = 0; l < L; ++l) spill_add(spill + ((size_t)g * NJ + (jr - l)) * 2, k[l]);
 }
 
+// ----------------------------------------------------------- row sources
+//
+// The aggregation loop reads its rows through a source, which loads a
+// tile's rows into registers and turns them into "virtual rows": one per
+// (row, aggregated column), each with its bin group and its value in the
+// accumulator type AT.
+
+// One value column: virtual row i is row i of the thread's rows.
+template <class KT, class VT, int VEC, int BLOCK>
+struct SrcCol {
+    static constexpr int RPT = ROWS_PER_THREAD;  // rows per thread and tile
+    static constexpr int NR = RPT;               // virtual rows per thread and tile
+    static constexpr int TILE = BLOCK * RPT;
+    struct Buf {
+        KT k[RPT];
+        VT v[RPT];
+    };
+    const KT* keys;
+    const VT* vals;
+    uint32_t off[RPT / VEC];
+    __device__ SrcCol(const KT* k, const VT* v) : keys(k), vals(v) {
+#pragma unroll
+        for (int u = 0; u < RPT / VEC; ++u) off[u] = (uint32_t)((u * BLOCK + threadIdx.x) * VEC);
+    }
+    __device__ __forceinline__ uint32_t load(Buf& b, int64_t base, int64_t end) const {
+        return load_tile<KT, VT, VEC, BLOCK>(keys, vals, base, end, b.k, b.v, off);
+    }
+    template <bool FULL, bool SLICE, class AT>
+    __device__ __forceinline__ void classify(const Buf& b, uint32_t inr, int G, int* gi, int* ji, bool& clean,
+                                             int64_t glo, int64_t Gfull) const {
+        classify_rows<FULL, SLICE, KT, VT, AT>(b.k, b.v, inr, G, gi, ji, clean, glo, Gfull);
+    }
+    template <class AT>
+    __device__ __forceinline__ uint32_t errors(const Buf& b, uint32_t inr, int64_t G) const {
+        return error_bits<KT, VT, AT>(b.k, b.v, inr, G);
+    }
+    template <class AT>
+    __device__ __forceinline__ AT value(const Buf& b, int i) const {
+        return (AT)b.v[i];
+    }
+};
+
+// NC value columns over one key column: virtual row c * RPT + r is column
+// c of row r, deposited into bin group c * Gc + key (the bins hold NC * Gc
+// groups).  Column c holds floats where bit c of f32mask is set, doubles
+// otherwise; floats widen exactly when AT is double.  Rows are loaded two
+// at a time (8- or 16-byte loads); every column must be aligned to two of
+// its elements and the keys to two keys.
+template <class KT, class AT, int NC, int BLOCK>
+struct SrcCols {
+    static constexpr int RPT = 8 / NC >= 2 ? 8 / NC : 2;
+    static constexpr int VEC = 2;
+    static constexpr int NR = RPT * NC;
+    static constexpr int TILE = BLOCK * RPT;
+    struct Buf {
+        KT k[RPT];
+        AT v[NC][RPT];
+    };
+    const KT* keys;
+    const void* vals[NC];
+    uint32_t f32mask;
+    int Gc;  // groups per column
+    uint32_t off[RPT / VEC];
+    __device__ SrcCols(const KT* k, const void* const* v, uint32_t fm, int gc) : keys(k), f32mask(fm), Gc(gc) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) vals[c] = v[c];
+#pragma unroll
+        for (int u = 0; u < RPT / VEC; ++u) off[u] = (uint32_t)((u * BLOCK + threadIdx.x) * VEC);
+    }
+    template <class VT>
+    __device__ __forceinline__ void load_col(const VT* __restrict__ vb, AT* out, bool full, uint32_t lim) const {
+        if (full) {
+#pragma unroll
+            for (int u = 0; u < RPT / VEC; ++u) {
+                VT x[VEC];
+                vload<VT, VEC>(vb + off[u], x);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) out[u * VEC + e] = (AT)x[e];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < RPT / VEC; ++u)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) out[u * VEC + e] = (off[u] + e < lim) ? (AT)vb[off[u] + e] : (AT)0;
+        }
+    }
+    __device__ __forceinline__ uint32_t load(Buf& b, int64_t base, int64_t end) const {
+        const bool full = base + (int64_t)TILE <= end;
+        const uint32_t lim = full ? 0u : (uint32_t)(end - base);
+        const KT* kb = keys + base;
+        uint32_t inr = 0;
+        if (full) {
+#pragma unroll
+            for (int u = 0; u < RPT / VEC; ++u) vload<KT, VEC>(kb + off[u], b.k + u * VEC);
+            inr = (1u << RPT) - 1;
+        } else {
+#pragma unroll
+            for (int u = 0; u < RPT / VEC; ++u)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const uint32_t row = off[u] + e;
+                    const bool in = row < lim;
+                    b.k[u * VEC + e] = in ? kb[row] : (KT)0;
+                    inr |= in ? 1u << (u * VEC + e) : 0u;
+                }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if ((f32mask >> c) & 1u)
+                load_col<float>(static_cast<const float*>(vals[c]) + base, b.v[c], full, lim);
+            else
+                load_col<double>(static_cast<const double*>(vals[c]) + base, b.v[c], full, lim);
+        }
+        return inr;
+    }
+    template <bool FULL, bool SLICE, class AT_>
+    __device__ __forceinline__ void classify(const Buf& b, uint32_t inr, int G, int* gi, int* ji, bool& clean,
+                                             int64_t, int64_t) const {
+        static_assert(!SLICE, "column sources have no group slices");
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            int gc[RPT], jc[RPT];
+            classify_rows<FULL, false, KT, AT, AT_, RPT>(b.k, b.v[c], inr, Gc, gc, jc, clean, 0, 0);
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                gi[c * RPT + r] = gc[r] == Gc ? G : c * Gc + gc[r];  // skipped rows: the trash slot G = NC * Gc
+                ji[c * RPT + r] = jc[r];
+            }
+        }
+    }
+    template <class AT_>
+    __device__ __forceinline__ uint32_t errors(const Buf& b, uint32_t inr, int64_t) const {
+        uint32_t e = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) e |= error_bits<KT, AT, AT_, RPT>(b.k, b.v[c], inr, Gc);
+        return e;
+    }
+    template <class AT_>
+    __device__ __forceinline__ AT_ value(const Buf& b, int i) const {
+        return (AT_)b.v[i / RPT][i % RPT];
+    }
+};
+
 constexpr int EPOCH_TILES = 16;  // tiles between synchronisations in epoch mode
 constexpr int QUIET_TILES = 1;   // quiet per-tile synchronisations before epoch mode
 
@@ -289,14 +435,15 @@ constexpr int QUIET_TILES = 1;   // quiet per-tile synchronisations before epoch
 // enables epoch mode, which needs the spill array, and the tracking of a
 // top shared by all groups (few groups, whose tops settle early); without
 // it every tile synchronises and rows read their group's top from LDS.
-template <class KT, class VT, class AT, int L, int VEC, bool EPOCH, bool SLICE = false, int BLOCK = AGG_BLOCK>
-__device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys, const VT* __restrict__ vals,
-                                                    int64_t c0, int64_t c1, int G, int R, unsigned char* smem,
-                                                    AggShared& sh, unsigned long long* __restrict__ spill,
-                                                    int64_t glo = 0, int64_t Gfull = 0) {
-    constexpr int TILE = BLOCK * ROWS_PER_THREAD;  // rows of one tile
+// The rows come from `src` (a row source above); G counts the bin groups.
+template <class Src, class AT, int L, bool EPOCH, bool SLICE, int BLOCK>
+__device__ __forceinline__ uint32_t aggregate_src(const Src& src, int64_t c0, int64_t c1, int G, int R,
+                                                  unsigned char* smem, AggShared& sh,
+                                                  unsigned long long* __restrict__ spill, int64_t glo, int64_t Gfull) {
+    constexpr int TILE = Src::TILE;  // rows of one tile
+    constexpr int NR = Src::NR;      // virtual rows per thread and tile
     typedef Fmt<AT> F;
-    constexpr int U = ROWS_PER_THREAD / VEC;
+    typedef typename Src::Buf Buf;
     long long* bins = reinterpret_cast<long long*>(smem);
     int2* TOP = reinterpret_cast<int2*>(bins + (size_t)(G + 1) * R * L);
     int* P = reinterpret_cast<int*>(TOP + (G + 1));
@@ -412,54 +559,47 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
 
     uint32_t err = 0;
 
-    uint32_t off[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) off[u] = (uint32_t)((u * BLOCK + tid) * VEC);
-
     // software pipeline: tiles base+TILE .. base+PREFETCH*TILE are in
     // flight (in registers) while tile `base` is processed
-    KT kb[PREFETCH + 1][ROWS_PER_THREAD];
-    VT vb[PREFETCH + 1][ROWS_PER_THREAD];
+    Buf buf[PREFETCH + 1];
     uint32_t inr[PREFETCH + 1];
 #pragma unroll
     for (int q = 0; q <= PREFETCH; ++q) inr[q] = 0;
 #pragma unroll
     for (int q = 0; q < PREFETCH; ++q)
-        if (c0 + (int64_t)q * TILE < c1)
-            inr[q] = load_tile<KT, VT, VEC, BLOCK>(keys, vals, c0 + (int64_t)q * TILE, c1, kb[q], vb[q], off);
+        if (c0 + (int64_t)q * TILE < c1) inr[q] = src.load(buf[q], c0 + (int64_t)q * TILE, c1);
 
     for (int64_t base = c0; base < c1; base += TILE) {
         const int64_t nb = base + (int64_t)PREFETCH * TILE;
         if (nb < c1)
-            inr[PREFETCH] = load_tile<KT, VT, VEC, BLOCK>(keys, vals, nb, c1, kb[PREFETCH], vb[PREFETCH], off);
+            inr[PREFETCH] = src.load(buf[PREFETCH], nb, c1);
         else
             inr[PREFETCH] = 0;
-        const KT* kc = kb[0];
-        const VT* vc = vb[0];
+        const Buf& bc = buf[0];
         const uint32_t inr_c = inr[0];
 
         // classify: group (trash slot G for skipped rows) and required top
-        int gi[ROWS_PER_THREAD], ji[ROWS_PER_THREAD];
+        int gi[NR], ji[NR];
         bool clean = true;  // no row of this lane is an error row
         if (base + TILE <= c1)
-            classify_rows<true, SLICE, KT, VT, AT>(kc, vc, inr_c, G, gi, ji, clean, glo, Gfull);
+            src.template classify<true, SLICE, AT>(bc, inr_c, G, gi, ji, clean, glo, Gfull);
         else
-            classify_rows<false, SLICE, KT, VT, AT>(kc, vc, inr_c, G, gi, ji, clean, glo, Gfull);
+            src.template classify<false, SLICE, AT>(bc, inr_c, G, gi, ji, clean, glo, Gfull);
         if (!clean)
-            err |= error_bits<KT, VT, AT>(kc, vc, base + TILE <= c1 ? (1u << ROWS_PER_THREAD) - 1 : inr_c, SLICE ? Gfull : G);
+            err |= src.template errors<AT>(bc, base + TILE <= c1 ? (1u << Src::RPT) - 1 : inr_c, SLICE ? Gfull : G);
 
         // tops of the rows' groups
-        int ai[ROWS_PER_THREAD];
-        uint32_t hi_[ROWS_PER_THREAD];
+        int ai[NR];
+        uint32_t hi_[NR];
         if (uni) {
 #pragma unroll
-            for (int i = 0; i < ROWS_PER_THREAD; ++i) {
+            for (int i = 0; i < NR; ++i) {
                 ai[i] = Ju;
                 hi_[i] = hu;
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < ROWS_PER_THREAD; ++i) {
+            for (int i = 0; i < NR; ++i) {
                 const int2 tp = TOP[gi[i]];
                 ai[i] = tp.x;
                 hi_[i] = (uint32_t)tp.y;
@@ -467,7 +607,7 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
         }
         bool raise = false;
 #pragma unroll
-        for (int i = 0; i < ROWS_PER_THREAD; ++i) raise = raise || (ji[i] > ai[i]);
+        for (int i = 0; i < NR; ++i) raise = raise || (ji[i] > ai[i]);
         if (!EPOCH && ahead) {
             // its rows' tops were raised and realigned with the previous tile
             ahead = false;
@@ -476,19 +616,18 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
             if (raise) {
                 sh.flag[sync % 3] = 1;
 #pragma unroll
-                for (int i = 0; i < ROWS_PER_THREAD; ++i)
+                for (int i = 0; i < NR; ++i)
                     if (ji[i] > ai[i]) raise_top(P, gi[i], ji[i], ai[i], sh, sync % 3);
             }
             if (!EPOCH) {
                 // look ahead: raise the tops of the prefetched tile's rows in
                 // the same synchronisation, so that tile needs none
-                int gn[ROWS_PER_THREAD], jn[ROWS_PER_THREAD];
+                int gn[NR], jn[NR];
                 bool cn = true;
-                classify_rows<false, SLICE, KT, VT, AT>(kb[PREFETCH], vb[PREFETCH], inr[PREFETCH], G, gn, jn, cn,
-                                                        glo, Gfull);
+                src.template classify<false, SLICE, AT>(buf[PREFETCH], inr[PREFETCH], G, gn, jn, cn, glo, Gfull);
                 bool rn = false;
 #pragma unroll
-                for (int i = 0; i < ROWS_PER_THREAD; ++i) {
+                for (int i = 0; i < NR; ++i) {
                     const int cur = TOP[gn[i]].x;
                     if (jn[i] > cur) {
                         raise_top(P, gn[i], jn[i], cur, sh, sync % 3);
@@ -506,20 +645,20 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
             if (moved) {
                 if (uni) {
 #pragma unroll
-                    for (int i = 0; i < ROWS_PER_THREAD; ++i) hi_[i] = hu;
+                    for (int i = 0; i < NR; ++i) hi_[i] = hu;
                 } else {
 #pragma unroll
-                    for (int i = 0; i < ROWS_PER_THREAD; ++i) hi_[i] = (uint32_t)TOP[gi[i]].y;
+                    for (int i = 0; i < NR; ++i) hi_[i] = (uint32_t)TOP[gi[i]].y;
                 }
             }
         } else if (raise) {
             // epoch mode: rows above their group's top go to the spill array
             int ns = 0;
 #pragma unroll
-            for (int i = 0; i < ROWS_PER_THREAD; ++i) {
+            for (int i = 0; i < NR; ++i) {
                 if (ji[i] > ai[i]) {
                     raise_top(P, gi[i], ji[i], ai[i], sh, sync % 3);
-                    spill_row<AT, L>(spill, gi[i], (AT)vc[i], ji[i]);
+                    spill_row<AT, L>(spill, gi[i], src.template value<AT>(bc, i), ji[i]);
                     gi[i] = G;  // nothing more for the bins
                     ++ns;
                 }
@@ -534,12 +673,27 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
                 hot = g0;
             }
         }
-        // extract and deposit; skipped rows (trash slot G: errors, zeros, and
-        // in slice mode the rows of other slices) issue no LDS atomics
+        // extract and deposit
+        if constexpr (EPOCH && !SLICE) {
+            // branch-free: skipped rows (errors; their units are arbitrary)
+            // add into the trash slot G, which is never read, so the rows'
+            // extraction chains can interleave
 #pragma unroll
-        for (int i = 0; i < ROWS_PER_THREAD; ++i) {
+            for (int i = 0; i < NR; ++i) {
+                long long k[L];
+                extract_from_hi<L>(src.template value<AT>(bc, i), hi_[i], k);
+                unsigned char* w = smem + __umul24((uint32_t)gi[i], gstride) + lane_off;
+#pragma unroll
+                for (int l = 0; l < L; ++l)
+                    atomicAdd(reinterpret_cast<unsigned long long*>(w + l * lstride), (unsigned long long)k[l]);
+            }
+        } else {
+        // skipped rows (trash slot G: errors, and in slice mode the rows of
+        // other slices) issue no LDS atomics
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
             long long k[L];
-            extract_from_hi<L>((AT)vc[i], hi_[i], k);
+            extract_from_hi<L>(src.template value<AT>(bc, i), hi_[i], k);
             unsigned char* w = smem + __umul24((uint32_t)gi[i], gstride) + lane_off;
             if (!EPOCH && gi[i] == hot) {
 #pragma unroll
@@ -550,6 +704,7 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
                     atomicAdd(reinterpret_cast<unsigned long long*>(w + l * lstride), (unsigned long long)k[l]);
             }
         }
+        }
         if (epoch_left > 0 && --epoch_left == 0) {
             int sp;
             synchronise(sp);
@@ -559,11 +714,7 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
         }
 #pragma unroll
         for (int q = 0; q < PREFETCH; ++q) {
-#pragma unroll
-            for (int i = 0; i < ROWS_PER_THREAD; ++i) {
-                kb[q][i] = kb[q + 1][i];
-                vb[q][i] = vb[q + 1][i];
-            }
+            buf[q] = buf[q + 1];
             inr[q] = inr[q + 1];
         }
     }
@@ -572,6 +723,17 @@ __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys,
     flush_hot();
     synchronise(sp);
     return err;
+}
+
+// One value column (the row source SrcCol).
+template <class KT, class VT, class AT, int L, int VEC, bool EPOCH, bool SLICE = false, int BLOCK = AGG_BLOCK>
+__device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys, const VT* __restrict__ vals,
+                                                    int64_t c0, int64_t c1, int G, int R, unsigned char* smem,
+                                                    AggShared& sh, unsigned long long* __restrict__ spill,
+                                                    int64_t glo = 0, int64_t Gfull = 0) {
+    const SrcCol<KT, VT, VEC, BLOCK> src(keys, vals);
+    return aggregate_src<SrcCol<KT, VT, VEC, BLOCK>, AT, L, EPOCH, SLICE, BLOCK>(src, c0, c1, G, R, smem, sh, spill,
+                                                                                 glo, Gfull);
 }
 
 // Folds a workgroup's aligned LDS level sums of group g (K[l * ks], top
