@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_agg_lds_lowcard_200M_g1024_L3_pmc.md")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_agg_cols_lowcard_200M_g1024_L3.md")
 # the sources that define the low-cardinality aggregation kernel, hashed in this order
 KERNEL_SOURCES = ("repro_cols.hip", "repro_lds.hpp", "repro_agg.hpp", "repro_device.hpp")
 
