@@ -67,16 +67,13 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_lds(const KT* __restrict__ ke
     const int64_t c0 = (int64_t)blockIdx.x * chunk;
     const int64_t c1 = (c0 + chunk < n) ? c0 + chunk : n;
     const uint32_t err = aggregate_range<KT, VT, AT, L, VEC, true>(keys, vals, c0, c1, G, R, smem, sh, spill);
-    const long long* bins = reinterpret_cast<const long long*>(smem);
+    long long* bins = reinterpret_cast<long long*>(smem);
     const int2* TOP = reinterpret_cast<const int2*>(bins + (size_t)(G + 1) * R * L);
+    fold_replicas<L, AGG_BLOCK>(bins, G, R);
     for (int g = threadIdx.x; g < G; g += AGG_BLOCK) {
         ptop[(size_t)blockIdx.x * G + g] = TOP[g].x;
 #pragma unroll
-        for (int l = 0; l < L; ++l) {
-            long long s = 0;
-            for (int r = 0; r < R; ++r) s += bins[((size_t)l * (G + 1) + g) * R + r];
-            pK[((size_t)blockIdx.x * L + l) * G + g] = s;
-        }
+        for (int l = 0; l < L; ++l) pK[((size_t)blockIdx.x * L + l) * G + g] = bins[((size_t)l * (G + 1) + g) * R];
     }
     report(status, err);
 }
@@ -699,9 +696,11 @@ int run_groupby(const void* keys, const void* values, int64_t n, int64_t G64, vo
         !allow_lds((const void*)k_agg_lds<KT, VT, AT, L, 1>, p.lds))
         return REPRO_EHIP;
     unsigned long long* spill = reinterpret_cast<unsigned long long*>(ws + p.spill_off);
-    hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(1024, (p.spill_words + 255) / 256)), dim3(256), 0, st,
-                       spill, p.spill_words);
-    LAUNCH_CHECK();
+    if (p.spill_used) {
+        hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(1024, (p.spill_words + 255) / 256)), dim3(256), 0,
+                           st, spill, p.spill_words);
+        LAUNCH_CHECK();
+    }
     prof_before(st);
     if (aligned)
         hipLaunchKernelGGL((k_agg_lds<KT, VT, AT, L, VEC>), dim3(p.nwg), dim3(AGG_BLOCK), p.lds, st, k, v, n, G, p.R,

@@ -116,6 +116,24 @@ __device__ __forceinline__ long long wave_sum64(long long x) {
     return x;
 }
 
+// Folds the R replicas (a power of two) of every LDS bin into replica 0 by
+// a tree of exact integer adds, all threads working on every round, so that
+// few groups with many replicas do not leave one thread summing them in
+// sequence.  Bins are [L][G+1][R] (layout below).  Call after the bins are
+// final; contains barriers (R uniform).
+template <int L, int BLOCK>
+__device__ __forceinline__ void fold_replicas(long long* bins, int G, int R) {
+    for (int h = R >> 1; h >= 1; h >>= 1) {
+        const int nwords = (G + 1) * L * h;  // adds of this round
+        const int sh = __builtin_ctz((unsigned)h);
+        for (int i = threadIdx.x; i < nwords; i += BLOCK) {
+            const int r = i & (h - 1), b = i >> sh;  // replica, bin (l, g)
+            bins[(size_t)b * R + r] += bins[(size_t)b * R + r + h];
+        }
+        __syncthreads();
+    }
+}
+
 __device__ __forceinline__ void report(uint32_t* status, uint32_t err) {
     err = wave_or(err);
     if (status && err && (threadIdx.x & 63) == 0) atomicOr(status, err);

@@ -195,18 +195,15 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
     const uint32_t err = aggregate_range<KT, VT, AT, L, VEC, EPOCH, true, BATCH_BLOCK>(
         static_cast<const KT*>(jb.keys), static_cast<const VT*>(jb.vals), r0, r1, Gs, R, smem, sh, spill, glo,
         jb.G);
-    const long long* bins = reinterpret_cast<const long long*>(smem);
+    long long* bins = reinterpret_cast<long long*>(smem);
     const int2* TOP = reinterpret_cast<const int2*>(bins + (size_t)(Gs + 1) * R * L);
+    fold_replicas<L, BATCH_BLOCK>(bins, Gs, R);
     AT* S = S_ptr<AT>(jb.states);
     long long* C = C_ptr<AT>(jb.states, jb.G, L);
     AT* out = static_cast<AT*>(jb.out);
     auto level_sums = [&](int g, long long* x) {
 #pragma unroll
-        for (int l = 0; l < L; ++l) {
-            long long s = 0;
-            for (int r = 0; r < R; ++r) s += bins[((size_t)l * (Gs + 1) + g) * R + r];
-            x[l] = s;
-        }
+        for (int l = 0; l < L; ++l) x[l] = bins[((size_t)l * (Gs + 1) + g) * R];
     };
     if (jb.nchunks == 1) {
         if (EPOCH) __threadfence();  // this workgroup's spill atomics, read back below

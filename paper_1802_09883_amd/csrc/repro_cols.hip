@@ -52,16 +52,13 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_cols(const KT* __restrict__ k
     const Src src(keys, vals.p, f32mask, G);
     const uint32_t err =
         aggregate_src<Src, double, L, true, false, AGG_BLOCK>(src, c0, c1, Gv, R, smem, sh, spill, 0, 0);
-    const long long* bins = reinterpret_cast<const long long*>(smem);
+    long long* bins = reinterpret_cast<long long*>(smem);
     const int2* TOP = reinterpret_cast<const int2*>(bins + (size_t)(Gv + 1) * R * L);
+    fold_replicas<L, AGG_BLOCK>(bins, Gv, R);
     for (int g = threadIdx.x; g < Gv; g += AGG_BLOCK) {
         ptop[(size_t)blockIdx.x * Gv + g] = TOP[g].x;
 #pragma unroll
-        for (int l = 0; l < L; ++l) {
-            long long s = 0;
-            for (int r = 0; r < R; ++r) s += bins[((size_t)l * (Gv + 1) + g) * R + r];
-            pK[((size_t)blockIdx.x * L + l) * Gv + g] = s;
-        }
+        for (int l = 0; l < L; ++l) pK[((size_t)blockIdx.x * L + l) * Gv + g] = bins[((size_t)l * (Gv + 1) + g) * R];
     }
     report(status, err);
 }
@@ -158,9 +155,11 @@ int run_cols(const KT* keys, const void* const* values, uint32_t f32mask, int64_
     int* ptop = reinterpret_cast<int*>(ws);
     long long* pK = reinterpret_cast<long long*>(ws + align_up((size_t)p.nwg * Gv * 4, 256));
     unsigned long long* spill = reinterpret_cast<unsigned long long*>(ws + p.spill_off);
-    hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(1024, (p.spill_words + 255) / 256)), dim3(256), 0, st,
-                       spill, p.spill_words);
-    LAUNCH_CHECK();
+    if (p.spill_used) {
+        hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(1024, (p.spill_words + 255) / 256)), dim3(256), 0,
+                           st, spill, p.spill_words);
+        LAUNCH_CHECK();
+    }
     prof_before(st);
     hipLaunchKernelGGL((k_agg_cols<KT, L, NC>), dim3(p.nwg), dim3(AGG_BLOCK), p.lds, st, keys, vp, f32mask, n, G,
                        p.R, p.chunk, ptop, pK, spill, status);

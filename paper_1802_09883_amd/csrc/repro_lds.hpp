@@ -48,6 +48,7 @@ __global__ void __launch_bounds__(256) k_zero(unsigned long long* __restrict__ p
 // caller's state the same way and writes the canonical (S, C).
 constexpr int M1_GROUPS = 64, M1_WAVES = 4;
 constexpr int M2_GROUPS = 16, M2_SLICES = 16;
+constexpr int64_t MERGE_DIRECT_MAX = 1 << 16;  // partials x groups merged by k_merge_l2 alone
 
 template <class AT, int L>
 __global__ void __launch_bounds__(M1_GROUPS* M1_WAVES)
@@ -116,7 +117,11 @@ struct ColStates {
     long long* C[REPRO_MAX_COLS];
 };
 
-template <class AT, int L>
+// RAW: the inputs are the workgroup partials themselves (qtop_ = their
+// tops, qhi_ = their level sums K, split here as hi = K >> CARRY, lo = K &
+// (2^CARRY - 1); qlo_ unused): one launch merges few partials.  spill_ is
+// null when no workgroup could spill (one tile per workgroup).
+template <class AT, int L, bool RAW>
 __global__ void __launch_bounds__(M2_GROUPS* M2_SLICES)
     k_merge_l2(const int* __restrict__ qtop_, const long long* __restrict__ qhi_, const long long* __restrict__ qlo_,
                int nq, int G, int gs, const unsigned long long* __restrict__ spill_, ColStates<AT> cs) {
@@ -129,14 +134,14 @@ __global__ void __launch_bounds__(M2_GROUPS* M2_SLICES)
     long long* __restrict__ C = cs.C[col];
     const int* __restrict__ qtop = qtop_ + (size_t)col * G;
     const long long* __restrict__ qhi = qhi_ + (size_t)col * G;
-    const long long* __restrict__ qlo = qlo_ + (size_t)col * G;
-    const unsigned long long* __restrict__ spill = spill_ + (size_t)col * G * NJ * 2;
+    const long long* __restrict__ qlo = RAW ? nullptr : qlo_ + (size_t)col * G;
     const int lane = threadIdx.x % M2_GROUPS, sl = threadIdx.x / M2_GROUPS;
     const int g = blockIdx.x * M2_GROUPS + lane;
     const bool gv = g < G;
     const int gg = gv ? g : 0;
     const int ts = state_top(S[gg]);
     int J = ts;
+#pragma unroll 4
     for (int q = sl; q < nq; q += M2_SLICES) J = max(J, qtop[(size_t)q * gs + gg]);
     sJ[sl][lane] = J;
     __syncthreads();
@@ -145,13 +150,20 @@ __global__ void __launch_bounds__(M2_GROUPS* M2_SLICES)
     long long hi[L], lo[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) hi[l] = lo[l] = 0;
+#pragma unroll 4
     for (int q = sl; q < nq; q += M2_SLICES) {
         const int d = J - qtop[(size_t)q * gs + gg];
         long long xh[L], xl[L];
 #pragma unroll
         for (int l = 0; l < L; ++l) {
-            xh[l] = qhi[((size_t)q * L + l) * gs + gg];
-            xl[l] = qlo[((size_t)q * L + l) * gs + gg];
+            if (RAW) {
+                const long long x = qhi[((size_t)q * L + l) * gs + gg];
+                xh[l] = x >> Fmt<AT>::CARRY;
+                xl[l] = x & ((1ll << Fmt<AT>::CARRY) - 1);
+            } else {
+                xh[l] = qhi[((size_t)q * L + l) * gs + gg];
+                xl[l] = qlo[((size_t)q * L + l) * gs + gg];
+            }
         }
 #pragma unroll
         for (int l = 0; l < L; ++l) {
@@ -181,11 +193,13 @@ __global__ void __launch_bounds__(M2_GROUPS* M2_SLICES)
             h += sH[w][l][lane];
             o += sLo[w][l][lane];
         }
-        // spilled units at lattice index J - l: H * 2^64 + w
-        const unsigned long long* sw = spill + ((size_t)g * NJ + (J - l)) * 2;
-        const i128 T = (i128)(long long)sw[1] * ((i128)1 << 64) + (i128)sw[0];
-        h += (long long)(T >> Fmt<AT>::CARRY);
-        o += (long long)(T & ((1ll << Fmt<AT>::CARRY) - 1));
+        if (spill_) {  // uniform
+            // spilled units at lattice index J - l: H * 2^64 + w
+            const unsigned long long* sw = spill_ + (((size_t)col * G + g) * NJ + (J - l)) * 2;
+            const i128 T = (i128)(long long)sw[1] * ((i128)1 << 64) + (i128)sw[0];
+            h += (long long)(T >> Fmt<AT>::CARRY);
+            o += (long long)(T & ((1ll << Fmt<AT>::CARRY) - 1));
+        }
         hi[l] = h;
         lo[l] = o;
     }
@@ -221,6 +235,7 @@ struct Plan {
     int R;          // LDS bin replicas
     int pb, nq;     // partials per level-1 merge block, level-1 results
     size_t spill_off, spill_words;  // spill array: G x (JMAX+1) x {w, H}
+    bool spill_used;  // a workgroup takes more than one tile (epoch mode, and so spills, possible)
     size_t lds;     // dynamic LDS bytes
     size_t ws;      // workspace bytes
 };
@@ -256,6 +271,9 @@ inline bool make_plan_lds(int64_t n, int64_t Gv, int L, int jmax, int64_t tile, 
     ws += 2 * align_up((size_t)p->nq * Gv * L * 8, 256);  // level-1 hi, lo
     p->spill_off = ws;
     p->spill_words = (size_t)Gv * (jmax + 1) * 2;
+    // epoch mode starts after a workgroup's first tile: with one tile per
+    // workgroup no row can spill, and the array is neither cleared nor read
+    p->spill_used = chunk > tile;
     ws += align_up(p->spill_words * 8, 256);
     p->ws = ws;
     return true;
@@ -273,12 +291,20 @@ int run_merge(const Plan& p, int G, int nc, unsigned char* ws, const ColStates<A
     long long* qhi = reinterpret_cast<long long*>(q + align_up((size_t)p.nq * Gv * 4, 256));
     long long* qlo = reinterpret_cast<long long*>(reinterpret_cast<unsigned char*>(qhi) +
                                                   align_up((size_t)p.nq * Gv * L * 8, 256));
+    const unsigned long long* spill =
+        p.spill_used ? reinterpret_cast<const unsigned long long*>(ws + p.spill_off) : nullptr;
+    const dim3 g2((G + M2_GROUPS - 1) / M2_GROUPS, nc);
+    if ((int64_t)p.nwg * Gv <= MERGE_DIRECT_MAX) {  // few partial groups: one launch
+        hipLaunchKernelGGL((k_merge_l2<AT, L, true>), g2, dim3(M2_GROUPS * M2_SLICES), 0, st, ptop, pK, nullptr,
+                           p.nwg, G, Gv, spill, cs);
+        LAUNCH_CHECK();
+        return REPRO_OK;
+    }
     hipLaunchKernelGGL((k_merge_l1<AT, L>), dim3((Gv + M1_GROUPS - 1) / M1_GROUPS, p.nq), dim3(M1_GROUPS * M1_WAVES),
                        0, st, ptop, pK, p.nwg, p.pb, Gv, qtop, qhi, qlo);
     LAUNCH_CHECK();
-    const unsigned long long* spill = reinterpret_cast<const unsigned long long*>(ws + p.spill_off);
-    hipLaunchKernelGGL((k_merge_l2<AT, L>), dim3((G + M2_GROUPS - 1) / M2_GROUPS, nc), dim3(M2_GROUPS * M2_SLICES), 0,
-                       st, qtop, qhi, qlo, p.nq, G, Gv, spill, cs);
+    hipLaunchKernelGGL((k_merge_l2<AT, L, false>), g2, dim3(M2_GROUPS * M2_SLICES), 0, st, qtop, qhi, qlo, p.nq, G,
+                       Gv, spill, cs);
     LAUNCH_CHECK();
     return REPRO_OK;
 }
