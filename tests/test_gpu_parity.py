@@ -303,6 +303,10 @@ def test_partitioned_uniform_keys_all_levels(L):
     check_case(keys, vals, G, L, True, "partitioned f64")
     v32 = np.ldexp(rng.standard_normal(n), rng.integers(-60, 60, n)).astype(np.float32)
     check_case(keys, v32, G, L, False, "partitioned float acc")
+    # f32 values widened into double accumulators: two atomics per row
+    w32 = np.ldexp(rng.standard_normal(n), rng.integers(-149, 128, n)).astype(np.float32)
+    w32[~np.isfinite(w32)] = 1.5
+    check_case(keys, w32, G, L, True, "partitioned f32 -> double")
 
 
 def test_partitioned_error_rows_and_resume():
