@@ -411,6 +411,9 @@ __global__ void __launch_bounds__(256) k_merge_part(const WorkItem* __restrict__
     if (g >= G) return;
     const int ts = state_top(S[g]);
     int J = ts;
+    // unrolled so that the loads of several work items are in flight at
+    // once: the hottest partitions (skewed keys) have dozens of items
+#pragma unroll 8
     for (int w = w0; w < w0 + it.nchunks; ++w) J = max(J, ptop[(size_t)w * GP + gl]);
     long long hi[L], lo[L];
 #pragma unroll
@@ -419,6 +422,7 @@ __global__ void __launch_bounds__(256) k_merge_part(const WorkItem* __restrict__
         hi[l] = (ls >= 0) ? C[(size_t)ls * G + g] : 0;
         lo[l] = (ls >= 0) ? state_lo(S[(size_t)ls * G + g]) : 0;
     }
+#pragma unroll 8
     for (int w = w0; w < w0 + it.nchunks; ++w) {
         const int d = J - ptop[(size_t)w * GP + gl];
         long long x[L];
