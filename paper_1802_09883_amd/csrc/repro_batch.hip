@@ -245,9 +245,12 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
             const int gg = (int)glo + g;
             long long hi[L], lo[L];
             int J = state_top_of(S, gg, jb.accumulate, L);
+            // unrolled: the loads of several chunks' partials in flight at once
+#pragma unroll 4
             for (int c = 0; c < jb.nchunks; ++c)
                 J = max(J, reinterpret_cast<const int*>(part0 + (size_t)c * pbytes)[g]);
             start_from_state<AT, L>(S, C, jb.G, gg, jb.accumulate, J, hi, lo);
+#pragma unroll 4
             for (int c = 0; c < jb.nchunks; ++c) {
                 const unsigned char* pp = part0 + (size_t)c * pbytes;
                 const long long* pK = reinterpret_cast<const long long*>(pp + align_up((size_t)jb.gs * 4, 8));
