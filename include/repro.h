@@ -204,6 +204,17 @@ int repro_derive_stats(const double* sum, const double* sumsq, const int64_t* co
                        double* var_samp, double* stddev_samp, hipStream_t stream);
 
 /*
+ * Expression columns for aggregates such as SUM(a * b) (RSum(expression,
+ * L), Sec. V-D) or the SUM(x * x) behind a variance (Sec. I):
+ * out[i] = a[i] * b[i] in double precision, one IEEE rounding to nearest
+ * even, no fused multiply-add.  a and b are float (at/bt = F32, widened
+ * exactly) or double columns of n entries; out is double[n] (may be a or b
+ * when that column is double).  n = 0 enqueues nothing.
+ */
+int repro_mul(const void* a, repro_scalar_t at, const void* b, repro_scalar_t bt, int64_t n, double* out,
+              hipStream_t stream);
+
+/*
  * ------------------------------------------------------------ batches
  *
  * Many independent GroupBy-SUMs (jobs) in one persistent kernel launch.
@@ -347,12 +358,15 @@ int repro_server_submit(repro_server* srv, const repro_query* q, int64_t* ticket
 /* Makes progress without blocking: retires finished queries (freeing their
  * memory and slot), then admits queued queries in order while they fit.
  * Writes up to `cap` completed tickets and their completion times (seconds
- * on the host's monotonic clock) and the counts of completed (in this call),
- * queued and running queries.  If enqueueing an admitted query's work fails
- * (REPRO_EHIP), that query is dropped: its slot and memory are freed once
- * what was enqueued has finished, and the error is returned. */
+ * on the host's monotonic clock); a finished query beyond `cap` stays in its
+ * slot and is reported by a later call.  Always writes the counts of
+ * completed (in this call, <= cap), queued and running queries, also when it
+ * returns an error.  If enqueueing an admitted query's work fails, that query
+ * is dropped: its slot and memory are freed once what was enqueued has
+ * finished, its ticket is written to *dropped (otherwise -1), admission stops
+ * for this call and REPRO_EHIP is returned.  Any output pointer may be NULL. */
 int repro_server_poll(repro_server* srv, int64_t* tickets, double* times, int cap, int* ndone, int* nqueued,
-                      int* nrunning);
+                      int* nrunning, int64_t* dropped);
 
 /* The host's monotonic clock (seconds) used for completion times. */
 double repro_server_clock(void);

@@ -63,6 +63,7 @@ def _load():
     lib.orc_round.argtypes = [i64, ctypes.c_uint64, i32, i32, i32, i32]
     lib.orc_round.restype = ctypes.c_double
     lib.orc_encode.argtypes = [i64, ctypes.c_uint64, i32, i32, vp, vp]
+    lib.orc_derive_stats.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -179,3 +180,17 @@ def encode(K: int, E: int, m: int):
     rc = _load().orc_encode(K >> 64, K & ((1 << 64) - 1), E, m, ctypes.byref(S), ctypes.byref(C))
     _check(rc, "encode")
     return S.value, C.value
+
+
+def derive_stats(sums, sumsq, counts):
+    """AVG, sample VAR and sample STDDEV per group from finalised SUM(x),
+    SUM(x*x) (float64) and exact COUNT (int64); returns three float64 arrays."""
+    s = np.ascontiguousarray(sums, dtype=np.float64)
+    q = np.ascontiguousarray(sumsq, dtype=np.float64)
+    c = np.ascontiguousarray(counts, dtype=np.int64)
+    G = s.shape[0]
+    if q.shape != (G,) or c.shape != (G,):
+        raise ValueError("sums, sumsq and counts must have one entry per group")
+    avg, var, sd = (np.empty(G, dtype=np.float64) for _ in range(3))
+    _check(_load().orc_derive_stats(_ptr(s), _ptr(q), _ptr(c), G, _ptr(avg), _ptr(var), _ptr(sd)), "derive_stats")
+    return avg, var, sd

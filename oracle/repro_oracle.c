@@ -490,6 +490,38 @@ int orc_finalize(const void* states, int64_t G, int T64, int L, void* out)
     return 0;
 }
 
+/* ------------------------------------------------- derived aggregates */
+
+/*
+ * AVG, sample VAR and sample STDDEV of every group from its finalised
+ * SUM(x), SUM(x*x) and exact COUNT: the aggregates that reduce to SUM
+ * (Sec. I).  The paper fixes no formula; the one taken here is the textbook
+ * sample variance (sum of squares minus sum times mean, over count - 1),
+ * evaluated as one fixed sequence of IEEE binary64 operations, each rounded
+ * to nearest even, with no fused multiply-add:
+ *     avg = s / c;   var = (q - s * avg) / (c - 1);   sd = sqrt(var).
+ * Because every input is reproducible and the sequence is fixed, so are the
+ * outputs.  A group with no row has avg = NaN; fewer than two rows give
+ * var = sd = NaN.  Any output pointer may be NULL.
+ */
+int orc_derive_stats(const double* sum, const double* sumsq, const int64_t* count, int64_t G, double* avg,
+                     double* var, double* sd)
+{
+    if (G < 1 || !sum || !sumsq || !count) return -1;
+    for (int64_t g = 0; g < G; ++g) {
+        double c = (double)count[g]; /* exact below 2^53 rows */
+        double s = sum[g], q = sumsq[g];
+        double m = s / c;
+        double p = s * m;
+        double u = q - p;
+        double v = u / (c - 1.0);
+        if (avg) avg[g] = count[g] > 0 ? m : NAN;
+        if (var) var[g] = count[g] > 1 ? v : NAN;
+        if (sd) sd[g] = count[g] > 1 ? sqrt(v) : NAN; /* IEEE sqrt: correctly rounded */
+    }
+    return 0;
+}
+
 /* --------------------------------------------- generic-format single sum */
 
 /*

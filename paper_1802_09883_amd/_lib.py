@@ -102,6 +102,8 @@ def load():
     lib.repro_groupby_count.argtypes = [vp, i32, i64, i64, vp, vp, vp]
     lib.repro_derive_stats.restype = ctypes.c_int
     lib.repro_derive_stats.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
+    lib.repro_mul.restype = ctypes.c_int
+    lib.repro_mul.argtypes = [vp, i32, vp, i32, i64, vp, vp]
     qp, scp = ctypes.POINTER(Query), ctypes.POINTER(ServerConfig)
     lib.repro_query_bytes.restype = sz
     lib.repro_query_bytes.argtypes = [qp, scp]
@@ -111,7 +113,8 @@ def load():
     lib.repro_server_submit.argtypes = [vp, qp, ctypes.POINTER(i64)]
     lib.repro_server_poll.restype = ctypes.c_int
     lib.repro_server_poll.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double), i32,
-                                      ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+                                      ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                      ctypes.POINTER(i64)]
     lib.repro_server_clock.restype = ctypes.c_double
     lib.repro_server_clock.argtypes = []
     lib.repro_server_destroy.restype = ctypes.c_int

@@ -51,9 +51,17 @@ def split_states(states: torch.Tensor, num_groups: int, L: int = 2, T=torch.floa
     return S, C
 
 
+def _new(shape, dtype, device, stream, zero=False):
+    """A tensor allocated on the stream its kernels run on (the caching
+    allocator then hands its memory to no other stream while they may run)."""
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    with torch.cuda.stream(s):
+        return (torch.zeros if zero else torch.empty)(shape, dtype=dtype, device=device)
+
+
 def state_init(num_groups: int, L: int = 2, T=torch.float64, device="cuda", stream=None) -> torch.Tensor:
     lib = _lib.load()
-    st = torch.empty(state_bytes(num_groups, L, T), dtype=torch.uint8, device=device)
+    st = _new(state_bytes(num_groups, L, T), torch.uint8, torch.device(device), stream)
     _lib.check(lib.repro_state_init(_vp(st), num_groups, _T(T), L, _stream(st.device, stream)), "state_init")
     return st
 
@@ -156,7 +164,7 @@ def plain_groupby_sum_cols(keys: torch.Tensor, columns, num_groups: int, outs=No
     keys = keys.contiguous()
     columns = [v.contiguous() for v in columns]
     if outs is None:
-        outs = [torch.zeros(num_groups, dtype=torch.float64, device=keys.device) for _ in columns]
+        outs = [_new(num_groups, torch.float64, keys.device, stream, zero=True) for _ in columns]
     nc = len(columns)
     vals = (ctypes.c_void_p * nc)(*[v.data_ptr() for v in columns])
     vts = (ctypes.c_int * nc)(*[_SCALAR[v.dtype] for v in columns])
@@ -189,26 +197,49 @@ def groupby_count(keys: torch.Tensor, num_groups: int, counts=None, status=None,
     lib = _lib.load()
     keys = keys.contiguous()
     if counts is None:
-        counts = torch.zeros(num_groups, dtype=torch.int64, device=keys.device)
+        counts = _new(num_groups, torch.int64, keys.device, stream, zero=True)
     _lib.check(lib.repro_groupby_count(_vp(keys), _KEY[keys.dtype], keys.numel(), num_groups, _vp(counts),
                                        _vp(status), _stream(keys.device, stream)), "groupby_count")
     return counts
 
 
-def groupby_stats(keys: torch.Tensor, values: torch.Tensor, num_groups: int, L: int = 2, stream=None):
+def mul(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """out[i] = a[i] * b[i] in float64, one IEEE rounding (float inputs widen
+    exactly): the expression column of an aggregate such as SUM(a * b)."""
+    for t in (a, b):
+        if t.dtype not in _SCALAR or t.dim() != 1 or not t.is_cuda:
+            raise TypeError("mul: 1-D float32/float64 device tensors")
+    if a.shape != b.shape or a.device != b.device:
+        raise ValueError("mul: columns of equal length on one GPU")
+    a, b = a.contiguous(), b.contiguous()
+    s = stream if stream is not None else torch.cuda.current_stream(a.device)
+    if out is None:
+        out = _new(a.numel(), torch.float64, a.device, s)
+    _lib.check(_lib.load().repro_mul(_vp(a), _SCALAR[a.dtype], _vp(b), _SCALAR[b.dtype], a.numel(), _vp(out),
+                                     ctypes.c_void_p(s.cuda_stream)), "mul")
+    return out
+
+
+def groupby_stats(keys: torch.Tensor, values: torch.Tensor, num_groups: int, L: int = 2, status=None, stream=None):
     """Reproducible AVG, sample VAR and sample STDDEV per group, derived from
-    the reproducible SUM(x), SUM(x*x) (x*x rounded once per row) and the
-    exact COUNT.  Returns a dict of float64 tensors (and the inputs)."""
+    the reproducible SUM(x), SUM(x*x) (x*x rounded once per row, in a HIP
+    kernel) and the exact COUNT.  Every step runs on ``stream`` (default: the
+    current one); ``status`` is OR-ed with the REPRO_ERR_* bits of the rows.
+    Returns a dict of device tensors."""
     lib = _lib.load()
-    values = values.to(torch.float64)
-    sq = values * values
-    s = finalize(groupby_sum(keys, values, num_groups, L, stream=stream), num_groups, L, stream=stream)
-    q = finalize(groupby_sum(keys, sq, num_groups, L, stream=stream), num_groups, L, stream=stream)
-    c = groupby_count(keys, num_groups, stream=stream)
-    avg, var, sd = (torch.empty(num_groups, dtype=torch.float64, device=keys.device) for _ in range(3))
-    _lib.check(lib.repro_derive_stats(_vp(s), _vp(q), _vp(c), num_groups, _vp(avg), _vp(var), _vp(sd),
-                                      _stream(keys.device, stream)), "derive_stats")
-    return {"sum": s, "sumsq": q, "count": c, "avg": avg, "var_samp": var, "stddev_samp": sd}
+    if keys.dtype not in _KEY or values.dtype not in _SCALAR or keys.shape != values.shape or keys.dim() != 1:
+        raise TypeError("keys int32/int64 and values float32/float64, 1-D of equal length")
+    dev = keys.device
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    sq = mul(values, values, stream=s)
+    c = _new(num_groups, torch.int64, dev, s, zero=True)
+    avg, var, sd = (_new(num_groups, torch.float64, dev, s) for _ in range(3))
+    sum_x = finalize(groupby_sum(keys, values, num_groups, L, status=status, stream=s), num_groups, L, stream=s)
+    sum_q = finalize(groupby_sum(keys, sq, num_groups, L, status=status, stream=s), num_groups, L, stream=s)
+    groupby_count(keys, num_groups, counts=c, status=status, stream=s)
+    _lib.check(lib.repro_derive_stats(_vp(sum_x), _vp(sum_q), _vp(c), num_groups, _vp(avg), _vp(var), _vp(sd),
+                                      ctypes.c_void_p(s.cuda_stream)), "derive_stats")
+    return {"sum": sum_x, "sumsq": sum_q, "count": c, "avg": avg, "var_samp": var, "stddev_samp": sd}
 
 
 def merge(dst: torch.Tensor, src: torch.Tensor, num_groups: int, L: int = 2, T=torch.float64, stream=None):
@@ -222,7 +253,7 @@ def finalize(states: torch.Tensor, num_groups: int, L: int = 2, T=torch.float64,
     """Finalised sums (type T) of every group."""
     lib = _lib.load()
     if out is None:
-        out = torch.empty(num_groups, dtype=T, device=states.device)
+        out = _new(num_groups, T, states.device, stream)
     _lib.check(lib.repro_finalize(_vp(states), num_groups, _T(T), L, _vp(out), _stream(states.device, stream)),
                "finalize")
     return out
@@ -234,7 +265,7 @@ def plain_groupby_sum(keys: torch.Tensor, values: torch.Tensor, num_groups: int,
     lib = _lib.load()
     keys, values = keys.contiguous(), values.contiguous()
     if out is None:
-        out = torch.zeros(num_groups, dtype=torch.float64, device=keys.device)
+        out = _new(num_groups, torch.float64, keys.device, stream, zero=True)
     rc = lib.repro_plain_groupby_sum(_vp(keys), _KEY[keys.dtype], _vp(values), _SCALAR[values.dtype], keys.numel(),
                                      num_groups, _vp(out), _vp(status), _stream(keys.device, stream))
     _lib.check(rc, "plain_groupby_sum")
@@ -406,6 +437,7 @@ class Server:
                                                 ctypes.byref(h)), "server_create")
         self.h = h
         self.live = {}  # ticket -> query (keeps its tensors alive)
+        self.completed = []  # completions reported by a poll that raised
 
     def query_bytes(self, spec):
         return int(self.lib.repro_query_bytes(ctypes.byref(spec.record()), ctypes.byref(self.cfg)))
@@ -417,15 +449,24 @@ class Server:
         return t.value
 
     def poll(self, cap=256):
-        """Returns ([(ticket, completion time)], queued, running)."""
+        """Returns ([(ticket, completion time)], queued, running).  If a
+        query's work could not be enqueued, the completions of this call are
+        kept in ``completed``, the dropped query is forgotten and
+        RuntimeError is raised naming its ticket."""
         tk = (ctypes.c_int64 * cap)()
         tm = (ctypes.c_double * cap)()
-        nd, nq, nr = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _lib.check(self.lib.repro_server_poll(self.h, tk, tm, cap, ctypes.byref(nd), ctypes.byref(nq),
-                                              ctypes.byref(nr)), "poll")
+        nd, nq, nr, dr = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64(-1)
+        rc = self.lib.repro_server_poll(self.h, tk, tm, cap, ctypes.byref(nd), ctypes.byref(nq), ctypes.byref(nr),
+                                        ctypes.byref(dr))
         done = [(tk[i], tm[i]) for i in range(min(nd.value, cap))]
         for t, _ in done:
             self.live.pop(t, None)
+        if dr.value >= 0:
+            self.live.pop(dr.value, None)
+        if rc != _lib.REPRO_OK:
+            self.completed.extend(done)
+            raise RuntimeError(f"poll: HIP error (code {rc}); dropped query {dr.value}; "
+                               f"{len(done)} completions kept in Server.completed")
         return done, nq.value, nr.value
 
     def clock(self):

@@ -309,14 +309,16 @@ __global__ void __launch_bounds__(PART_BLOCK)
             if (i < c1) {
                 const int64_t key = kk[u];
                 VT v = vv[u];
+                // every row's value is classified, whatever its key, so the
+                // status bits are those of the LDS path
+                if (!finite_val(v)) {
+                    err |= ERR_NONFINITE;
+                    v = (VT)0;
+                } else if (v != (VT)0 && jreq_raw<AT>(frexp_raw(v)) > Fm::JMAX) {
+                    err |= ERR_RANGE;
+                    v = (VT)0;
+                }
                 if ((uint64_t)key < (uint64_t)G) {
-                    if (!finite_val(v)) {
-                        err |= ERR_NONFINITE;
-                        v = (VT)0;
-                    } else if (v != (VT)0 && jreq_raw<AT>(frexp_raw(v)) > Fm::JMAX) {
-                        err |= ERR_RANGE;
-                        v = (VT)0;
-                    }
                     pi[u] = (int)(key >> gp_shift);
                     lk[u] = (uint16_t)((uint32_t)key & gmask);
                     vv[u] = v;

@@ -37,11 +37,21 @@ constexpr size_t SERVE_ALIGN = 256;
 
 inline size_t up(size_t x) { return (x + SERVE_ALIGN - 1) / SERVE_ALIGN * SERVE_ALIGN; }
 
-// out[i] = a[i] * b[i], one IEEE rounding (the build disables contraction).
-__global__ void __launch_bounds__(256) k_mul(const double* __restrict__ a, const double* __restrict__ b,
+// out[i] = a[i] * b[i] in double precision, one IEEE rounding (the build
+// disables contraction); float inputs widen exactly first.
+template <class TA, class TB>
+__global__ void __launch_bounds__(256) k_mul(const TA* __restrict__ a, const TB* __restrict__ b,
                                              double* __restrict__ out, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        out[i] = a[i] * b[i];
+        out[i] = (double)a[i] * (double)b[i];
+}
+
+template <class TA, class TB>
+int launch_mul(const void* a, const void* b, int64_t n, double* out, hipStream_t st) {
+    const int64_t blocks = std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL((k_mul<TA, TB>), dim3((unsigned)blocks), dim3(256), 0, st, static_cast<const TA*>(a),
+                       static_cast<const TB*>(b), out, n);
+    return hipGetLastError() == hipSuccess ? REPRO_OK : REPRO_EHIP;
 }
 
 // First-fit allocator over [0, size) with coalescing; offsets 256-aligned.
@@ -150,10 +160,11 @@ bool layout_query(const repro_query* q, int64_t chunk_cfg, bool batch_path, Quer
             ly->image_bytes = img;
         }
     }
-    if (!ly->batch)
-        ly->ws_bytes = q->n > 0 ? repro_workspace_bytes(std::min<int64_t>(q->n, ly->chunk), q->num_groups, REPRO_I32,
-                                                        REPRO_F64, REPRO_F64, q->L)
-                                : 0;
+    if (!ly->batch && q->n > 0) {
+        ly->ws_bytes = repro_workspace_bytes(std::min<int64_t>(q->n, ly->chunk), q->num_groups, REPRO_I32, REPRO_F64,
+                                             REPRO_F64, q->L);
+        if (ly->ws_bytes == 0) return false;  // no plan for these sizes: refused at submission
+    }
     size_t off = 0;
     for (int a = 0; a < q->naggs; ++a) {
         ly->off_state[a] = off;
@@ -215,10 +226,8 @@ int enqueue_query(repro_server* s, Slot& sl, const repro_query& q, const QueryLa
         vals[a] = q.cols[q.agg_a[a]];
         if (q.agg_b[a] >= 0 && q.n > 0) {
             double* prod = reinterpret_cast<double*>(base + ly.off_prod[a]);
-            const int64_t blocks = std::min<int64_t>(4096, (q.n + 255) / 256);
-            hipLaunchKernelGGL(k_mul, dim3((unsigned)blocks), dim3(256), 0, st, q.cols[q.agg_a[a]], q.cols[q.agg_b[a]],
-                               prod, q.n);
-            if (hipGetLastError() != hipSuccess) return REPRO_EHIP;
+            if (launch_mul<double, double>(q.cols[q.agg_a[a]], q.cols[q.agg_b[a]], q.n, prod, st) != REPRO_OK)
+                return REPRO_EHIP;
             vals[a] = prod;
         }
     }
@@ -256,6 +265,18 @@ int enqueue_query(repro_server* s, Slot& sl, const repro_query& q, const QueryLa
 }  // namespace
 
 extern "C" {
+
+int repro_mul(const void* a, repro_scalar_t at, const void* b, repro_scalar_t bt, int64_t n, double* out,
+              hipStream_t stream) {
+    if (n < 0 || (at != REPRO_F32 && at != REPRO_F64) || (bt != REPRO_F32 && bt != REPRO_F64)) return REPRO_EINVAL;
+    if (n == 0) return REPRO_OK;
+    if (!a || !b || !out) return REPRO_EINVAL;
+    if (at == REPRO_F64)
+        return bt == REPRO_F64 ? launch_mul<double, double>(a, b, n, out, stream)
+                               : launch_mul<double, float>(a, b, n, out, stream);
+    return bt == REPRO_F64 ? launch_mul<float, double>(a, b, n, out, stream)
+                           : launch_mul<float, float>(a, b, n, out, stream);
+}
 
 size_t repro_query_bytes(const repro_query* q, const repro_server_config* cfg) {
     QueryLayout ly;
@@ -302,27 +323,31 @@ int repro_server_submit(repro_server* s, const repro_query* q, int64_t* ticket) 
 }
 
 int repro_server_poll(repro_server* s, int64_t* tickets, double* times, int cap, int* ndone, int* nqueued,
-                      int* nrunning) {
-    if (!s) return REPRO_EINVAL;
+                      int* nrunning, int64_t* dropped) {
+    if (!s || cap < 0) return REPRO_EINVAL;
+    int rc = REPRO_OK;
     int done = 0;
-    // retire
+    if (dropped) *dropped = -1;
+    // retire: a finished query is reported and its slot freed only while
+    // there is room in the caller's arrays; the others stay busy and are
+    // reported by a later poll
     for (Slot& sl : s->slots) {
-        if (!sl.busy) continue;
+        if (!sl.busy || done >= cap) continue;
         const hipError_t e = hipEventQuery(sl.done);
         if (e == hipErrorNotReady) continue;
-        if (e != hipSuccess) return REPRO_EHIP;
-        const double t = now_s();
-        if (done < cap) {
-            if (tickets) tickets[done] = sl.ticket;
-            if (times) times[done] = t;
+        if (e != hipSuccess) {
+            rc = REPRO_EHIP;
+            break;
         }
+        if (tickets) tickets[done] = sl.ticket;
+        if (times) times[done] = now_s();
         ++done;
         s->alloc.release(sl.off, sl.bytes);
         sl.busy = false;
         sl.ticket = -1;
     }
     // admit, in order, while a slot and memory are free
-    while (!s->queue.empty()) {
+    while (rc == REPRO_OK && !s->queue.empty()) {
         Slot* free_slot = nullptr;
         for (Slot& sl : s->slots)
             if (!sl.busy) {
@@ -332,7 +357,10 @@ int repro_server_poll(repro_server* s, int64_t* tickets, double* times, int cap,
         if (!free_slot) break;
         const Pending& p = s->queue.front();
         QueryLayout ly;
-        if (!layout_query(&p.q, s->chunk, s->batch_path, &ly)) return REPRO_EINVAL;
+        if (!layout_query(&p.q, s->chunk, s->batch_path, &ly)) {  // validated at submission: cannot happen
+            rc = REPRO_EINVAL;
+            break;
+        }
         size_t off = 0;
         if (!s->alloc.alloc(ly.total, &off)) break;  // wait for memory
         free_slot->busy = true;
@@ -341,15 +369,15 @@ int repro_server_poll(repro_server* s, int64_t* tickets, double* times, int cap,
         free_slot->bytes = ly.total;
         const repro_query q = p.q;
         s->queue.pop_front();
-        const int rc = enqueue_query(s, *free_slot, q, ly);
-        if (rc != REPRO_OK) {
+        if (enqueue_query(s, *free_slot, q, ly) != REPRO_OK) {
             // drop the query: let what was enqueued finish before its memory
-            // and slot are reused, then report the error
+            // and slot are reused, report its ticket and stop admitting
             (void)hipStreamSynchronize(free_slot->stream);
             s->alloc.release(free_slot->off, free_slot->bytes);
+            if (dropped) *dropped = free_slot->ticket;
             free_slot->busy = false;
             free_slot->ticket = -1;
-            return rc;
+            rc = REPRO_EHIP;
         }
     }
     if (ndone) *ndone = done;
@@ -359,7 +387,7 @@ int repro_server_poll(repro_server* s, int64_t* tickets, double* times, int cap,
         for (const Slot& sl : s->slots) r += sl.busy;
         *nrunning = r;
     }
-    return REPRO_OK;
+    return rc;
 }
 
 int repro_server_destroy(repro_server* s) {

@@ -56,6 +56,14 @@ def test_invalid_arguments_return_einval_without_gpu(lib):
     assert lib.repro_groupby_sum(null, 0, null, 1, 0, 4, 1, 2, p, null, 0, null, null) == _lib.REPRO_OK
     assert lib.repro_merge(p, p, 4, 1, 2, null) == _lib.REPRO_EINVAL
     assert lib.repro_finalize(p, 4, 1, 2, null, null) == _lib.REPRO_EINVAL
+    # products: negative n, unknown type, missing output; n = 0 is a no-op
+    assert lib.repro_mul(p, _lib.F64, p, _lib.F64, -1, p, null) == _lib.REPRO_EINVAL
+    assert lib.repro_mul(p, 7, p, _lib.F64, 10, p, null) == _lib.REPRO_EINVAL
+    assert lib.repro_mul(p, _lib.F32, p, _lib.F64, 10, null, null) == _lib.REPRO_EINVAL
+    assert lib.repro_mul(null, _lib.F32, null, _lib.F64, 0, null, null) == _lib.REPRO_OK
+    # a server poll without a server, or with a negative capacity
+    n = ctypes.c_int(5)
+    assert lib.repro_server_poll(null, None, None, 4, ctypes.byref(n), None, None, None) == _lib.REPRO_EINVAL
 
 
 def _jobs(specs):

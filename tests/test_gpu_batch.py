@@ -183,21 +183,74 @@ def test_batch_invalid_jobs_are_rejected():
         api.batch_prepare([api.Job(k, dev(np.zeros(10)), 4, 2, st)], T=torch.float32)  # f64 -> float narrows
 
 
-def test_batch_full_size_512_jobs_sampled():
+def test_batch_full_size_512_jobs():
     """The batched workload at its full size (512 jobs, rows log-uniform
-    1e3..1e7, groups log-uniform 1..2^16, L in {2, 3}); every 8th job and
-    the largest ones are checked against the oracle."""
+    1e3..1e7, groups log-uniform 1..2^16, L in {2, 3}): every job's states
+    and finalised sums against the oracle, tolerance 0."""
     rows, groups, Ls = WL.batched_jobs()
     say(f"case full batch: {len(rows)} jobs, {int(rows.sum())} rows")
     specs = [(*WL.batched_job(int(r), int(g), j), int(g), int(l)) for j, (r, g, l) in enumerate(zip(rows, groups, Ls))]
-    jobs, priors = make_batch(specs, with_out=False)
+    jobs, priors = make_batch(specs, with_out=True)
     status = torch.zeros(1, dtype=torch.int32, device="cuda")
     api.batch_groupby_sum(jobs, status=status)
     torch.cuda.synchronize()
     assert int(status.item()) == 0
-    pick = sorted(set(range(0, len(jobs), 8)) | set(np.argsort(rows)[-4:].tolist()) |
-                  set(np.argsort(groups)[-4:].tolist()))
-    check_jobs([jobs[i] for i in pick], [specs[i] for i in pick], [priors[i] for i in pick], 0, "full batch")
+    want_status = 0
+    for i, (job, (keys, vals, G, L)) in enumerate(zip(jobs, specs)):
+        ref, st = O.groupby_sum(keys, vals, G, L, True, threads=16)
+        want_status |= st
+        Sg, Cg = O.split_states(job.states.cpu().numpy(), G, L, True)
+        So, Co = O.split_states(ref, G, L, True)
+        assert np.array_equal(Sg.view(np.uint8), So.view(np.uint8)) and np.array_equal(Cg, Co), \
+            f"full batch: job {i} (n={len(keys)}, G={G}, L={L}) states differ from the oracle"
+        assert np.array_equal(job.out.cpu().numpy().view(np.uint8), O.finalize(ref, G, L).view(np.uint8)), \
+            f"full batch: job {i} finalised sums differ"
+        if i % 64 == 63:
+            say(f"  checked {i + 1} jobs")
+    assert want_status == 0
+
+
+def _headroom_values(n, L, sign):
+    """Values whose units sit just below 2^(W-1) = 2^39 at every level they
+    reach, all of one sign, in one group at top index 26 (E = 18, grid of the
+    first level 2^-34): b = 32 - 2^-35 - 2^-48 has units 2^39 - 1 and
+    2^39 - 2^26; b * 2^-40 has units 0, 2^39 - 1 and 2^39 - 2^26."""
+    b = 32.0 - 2.0 ** -35 - 2.0 ** -48
+    if L <= 2:
+        v = np.full(n, b)
+    else:
+        v = np.empty(n)
+        v[0::2], v[1::2] = b, b * 2.0 ** -40
+    return sign * v
+
+
+@pytest.mark.parametrize("L,sign", [(2, 1.0), (2, -1.0), (3, 1.0), (4, -1.0)])
+def test_carry_headroom_one_item_of_2_23_rows(L, sign):
+    """The tiling bound of Sec. III-D taken as at most 2^23 rows into one
+    workgroup's int64 level words: one batch item of exactly 2^23 rows of one
+    group whose units are all just below 2^39 and of one sign, so a level
+    word reaches about 2^62.  States and sums match the oracle bit for bit."""
+    n = 1 << 23
+    vals = _headroom_values(n, L, sign)
+    keys = np.zeros(n, np.int32)
+    units = O.extract(float(abs(vals[0])), 26, L, 52, 40, -1022)
+    assert units[0] == 2 ** 39 - 1 and units[1] == 2 ** 39 - 2 ** 26
+    say(f"case headroom: {n} rows, one group, L={L}, sign {sign:+.0f}, one item")
+    st = torch.empty(api.state_bytes(1, L), dtype=torch.uint8, device="cuda")
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    run = api.batch_groupby_sum([api.Job(dev(keys), dev(vals), 1, L, st, out)], config={"chunk_rows": n},
+                                status=status)
+    torch.cuda.synchronize()
+    assert run.plan.items == 1, "the job must run as one item of 2^23 rows"
+    ref, rst = O.groupby_sum(keys, vals, 1, L, True, threads=8)
+    assert int(status.item()) == rst == 0
+    Sg, Cg = O.split_states(st.cpu().numpy(), 1, L, True)
+    So, Co = O.split_states(ref, 1, L, True)
+    assert np.array_equal(Sg.view(np.uint8), So.view(np.uint8)) and np.array_equal(Cg, Co)
+    # the level sums did reach about 2^62 (C counts 2^50 units each)
+    assert int(np.abs(Co).max()) >= (2 ** 61) >> 50
+    assert out.cpu().numpy().view(np.uint64)[0] == O.finalize(ref, 1, L).view(np.uint64)[0]
 
 
 @pytest.mark.parametrize("T64", [True, False])

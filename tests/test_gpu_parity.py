@@ -174,6 +174,63 @@ def test_error_rows_status_and_skip():
     check_case(k32, v32, 2, 2, False, "error rows f32")
 
 
+@pytest.mark.parametrize("G", [4, 1000, 5484, 5485, 300_000])
+@pytest.mark.parametrize("T64", [True, False])
+def test_bad_key_rows_carry_their_value_status(G, T64):
+    """The only non-finite and out-of-domain values sit on rows whose keys are
+    out of range: the status word still holds KEY | NONFINITE | RANGE, as the
+    oracle classifies every row's value whatever its key, on the LDS path
+    (G up to 5484 at L = 2) and on the partitioned path (above)."""
+    rng = np.random.default_rng([61, G, T64])
+    n = 200_003
+    keys = rng.integers(0, G, n).astype(np.int64)
+    big = 2.0 ** 1006 if T64 else 2.0 ** 121
+    vals = np.ldexp(rng.standard_normal(n), rng.integers(-60, 60, n))
+    bad = rng.choice(n, 60, replace=False)
+    keys[bad[:20]] = G + 7
+    keys[bad[20:40]] = -3
+    keys[bad[40:]] = G
+    vals[bad[:10]] = np.nan
+    vals[bad[10:20]] = np.inf
+    vals[bad[20:30]] = -big
+    vals[bad[30:40]] = big
+    vals = vals if T64 else vals.astype(np.float32)
+    st = check_case(keys, vals, G, 2, T64, f"bad-key rows only (G={G})")
+    orc_status = O.groupby_sum(keys, vals, G, 2, T64)[1]
+    assert orc_status == 7, orc_status  # KEY | NONFINITE | RANGE
+    # only a bad key: KEY alone
+    k2 = keys.copy()
+    v2 = np.where(np.isfinite(vals) & (np.abs(vals) < big), vals, 1.0).astype(vals.dtype)
+    check_case(k2, v2, G, 2, T64, f"bad keys, finite values (G={G})")
+    del st
+
+
+def test_bad_key_rows_status_other_paths():
+    """The same rows through the multi-column call, a batch and the
+    ungrouped sum (whose rows have no key: value bits only)."""
+    rng = np.random.default_rng(62)
+    n, G = 100_000, 1024
+    keys = rng.integers(0, G, n).astype(np.int32)
+    v = np.ldexp(rng.standard_normal(n), rng.integers(-30, 30, n))
+    keys[[5, 6, 7]] = G + 1
+    v[5], v[6], v[7] = np.nan, 2.0 ** 1006, -np.inf
+    want = O.groupby_sum(keys, v, G, 3)[1]
+    assert want == 7
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    api.groupby_sum_cols(dev(keys), [dev(v), dev(v.astype(np.float32))], G, 3, status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 7 | O.groupby_sum(keys, v.astype(np.float32), G, 3)[1]
+    status.zero_()
+    st = torch.empty(api.state_bytes(G, 3), dtype=torch.uint8, device="cuda")
+    api.batch_groupby_sum([api.Job(dev(keys), dev(v), G, 3, st)], status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == want
+    status.zero_()
+    api.sum(dev(v), 3, status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == O.groupby_sum(np.zeros(n, np.int32), v, 1, 3)[1] == 6
+
+
 # ------------------------------------------- schedule / resume / merge
 
 def test_chunked_calls_and_host_roundtrip_resume():

@@ -166,3 +166,36 @@ def test_status_bits_and_empty_query():
         assert np.array_equal(o.cpu().numpy(), O.finalize(st, G, 3))
     for o in empty.out:
         assert o.cpu().numpy().tolist() == [0.0] * 7
+
+
+def test_poll_reports_every_completion_within_cap():
+    """Completions beyond the caller's `cap` stay in their slots and are
+    reported by later polls: no ticket is lost, the counts are always
+    written, and no poll reports more than `cap`."""
+    n, G = 20_000, 64
+    keys = torch.from_numpy(WL.served_keys(n, G, 0, salt=5)).cuda()
+    cols = [torch.from_numpy(np.ascontiguousarray(c)).cuda() for c in WL.decimal_columns(n, 2, salt=5)]
+    specs = [api.QuerySpec(keys, cols, G, [(0, None), (0, 1)], L=2) for _ in range(6)]
+    srv = api.Server(1 << 28, slots=6)
+    try:
+        for s in specs:
+            srv.submit(s)
+        _, nq, nr = srv.poll(cap=6)  # admits all six
+        assert nq == 0 and nr == 6
+        torch.cuda.synchronize()
+        time.sleep(0.01)
+        seen = []
+        for _ in range(50):
+            done, nq, nr = srv.poll(cap=2)
+            assert len(done) <= 2
+            seen += [t for t, _ in done]
+            if len(seen) == 6:
+                break
+        assert sorted(seen) == list(range(6)) and nr == 0 and nq == 0
+        assert not srv.live
+    finally:
+        srv.close()
+    want = O.finalize(O.groupby_sum(keys.cpu().numpy(), cols[0].cpu().numpy(), G, 2)[0], G, 2)
+    for s in specs:
+        assert np.array_equal(s.out[0].cpu().numpy(), want)
+

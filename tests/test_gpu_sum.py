@@ -127,39 +127,65 @@ def test_accuracy_within_bound(dist, n):
 
 def test_counts_and_derived_statistics():
     """COUNT is exact; AVG / VAR / STDDEV derived from reproducible sums are
-    bit-identical to the same formula applied to the oracle's sums, and do
-    not change with the row order."""
+    bit-identical to the oracle's derivation (the same fixed IEEE sequence,
+    square root included) from the oracle's sums, and do not change with the
+    row order.  Tolerance 0."""
     rng = np.random.default_rng(9)
     n, G = 2_000_003, 5000
     keys = rng.integers(0, G, n).astype(np.int32)
     keys[:10] = G - 1  # group G-1 has rows; make one group empty and one with a single row
     keys[keys == 7] = 8
     keys[11] = 7
+    keys[keys == 12] = 13  # group 12 empty
     vals = np.round(np.exp(rng.uniform(0, np.log(1e6), n)) * 100) / 100
-    out = api.groupby_stats(torch.from_numpy(keys).cuda(), torch.from_numpy(vals).cuda(), G, L=2)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = api.groupby_stats(torch.from_numpy(keys).cuda(), torch.from_numpy(vals).cuda(), G, L=2, status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
     cnt = np.bincount(keys, minlength=G)
     assert np.array_equal(out["count"].cpu().numpy(), cnt)
     s_ref = O.finalize(O.groupby_sum(keys, vals, G, 2, threads=8)[0], G, 2)
     q_ref = O.finalize(O.groupby_sum(keys, vals * vals, G, 2, threads=8)[0], G, 2)
     assert np.array_equal(out["sum"].cpu().numpy(), s_ref) and np.array_equal(out["sumsq"].cpu().numpy(), q_ref)
-    with np.errstate(invalid="ignore", divide="ignore"):
-        c = cnt.astype(np.float64)
-        m = s_ref / c
-        v = (q_ref - s_ref * m) / (c - 1.0)
-    m = np.where(cnt > 0, m, np.nan)
-    v = np.where(cnt > 1, v, np.nan)
-    got_m, got_v, got_s = (out[k].cpu().numpy() for k in ("avg", "var_samp", "stddev_samp"))
-    assert np.array_equal(got_m, m, equal_nan=True)
-    assert np.array_equal(got_v, v, equal_nan=True)
-    # sqrt: within one ulp of the correctly rounded root (the device routine
-    # is deterministic; its last bit is not part of the contract)
-    want_s = np.sqrt(v)
-    ok = np.isnan(want_s) == np.isnan(got_s)
-    fin = ~np.isnan(want_s)
-    assert ok.all() and np.all(np.abs(got_s[fin] - want_s[fin]) <= np.spacing(want_s[fin]))
+    m, v, sd = O.derive_stats(s_ref, q_ref, cnt)
+    for name, want in (("avg", m), ("var_samp", v), ("stddev_samp", sd)):
+        got = out[name].cpu().numpy()
+        assert np.array_equal(np.isnan(got), np.isnan(want)), name
+        fin = ~np.isnan(want)
+        assert np.array_equal(got[fin].view(np.uint64), want[fin].view(np.uint64)), f"{name} differs from the oracle"
+    got_m, got_v = out["avg"].cpu().numpy(), out["var_samp"].cpu().numpy()
     assert np.isnan(got_v[7]) and not np.isnan(got_m[7])  # one row: AVG defined, VAR not
+    assert np.isnan(got_m[12])  # no row: AVG undefined
     # another order of the same rows: the same bits
     perm = rng.permutation(n)
     out2 = api.groupby_stats(torch.from_numpy(keys[perm]).cuda(), torch.from_numpy(vals[perm]).cuda(), G, L=2)
     for k in ("avg", "var_samp", "stddev_samp"):
         assert np.array_equal(out2[k].cpu().numpy().view(np.uint64), out[k].cpu().numpy().view(np.uint64))
+
+
+def test_derived_statistics_float_values_side_stream_and_status():
+    """float32 values (widened exactly; their squares are exact in double),
+    a non-default stream, and error rows reported through the status word."""
+    rng = np.random.default_rng(10)
+    n, G = 300_001, 700
+    keys = rng.integers(0, G, n).astype(np.int64)
+    vals = np.ldexp(rng.standard_normal(n), rng.integers(-20, 20, n)).astype(np.float32)
+    keys[3], vals[4] = G + 1, np.nan
+    side = torch.cuda.Stream()
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    kt, vt = torch.from_numpy(keys).cuda(), torch.from_numpy(vals).cuda()
+    side.wait_stream(torch.cuda.current_stream())
+    out = api.groupby_stats(kt, vt, G, L=3, status=status, stream=side)
+    side.synchronize()
+    ok = (keys >= 0) & (keys < G)
+    s_ref, st1 = O.groupby_sum(keys, vals, G, 3)
+    q_ref, _ = O.groupby_sum(keys, vals.astype(np.float64) ** 2, G, 3)
+    s_ref, q_ref = O.finalize(s_ref, G, 3), O.finalize(q_ref, G, 3)
+    cnt = np.bincount(keys[ok], minlength=G)
+    assert int(status.item()) == st1 == (1 | 2)
+    assert np.array_equal(out["count"].cpu().numpy(), cnt)
+    for name, want in zip(("avg", "var_samp", "stddev_samp"), O.derive_stats(s_ref, q_ref, cnt)):
+        got = out[name].cpu().numpy()
+        assert np.array_equal(np.isnan(got), np.isnan(want)), name
+        fin = ~np.isnan(want)
+        assert np.array_equal(got[fin].view(np.uint64), want[fin].view(np.uint64)), name

@@ -398,3 +398,69 @@ def test_error_rows_are_skipped_with_status_bits():
     assert status == O.ERR_RANGE
     with pytest.raises(RuntimeError):
         O.groupby_sum(np.array([0], np.int32), np.array([1.0]), 1, 2, T64=False)
+
+
+# ------------------------------------------- derived aggregates (Sec. I)
+
+def _rne_sqrt_ok(v: float, y: float) -> bool:
+    """y is the binary64 nearest to sqrt(v): (y - h)^2 < v < (y + h)^2 with
+    h half an ulp of y, in exact rationals (a square root of a binary64 value
+    is never a midpoint, so no tie needs breaking)."""
+    if v == 0.0:
+        return y == 0.0
+    fy, fv = Fraction(y), Fraction(v)
+    h = Fraction(math.ulp(y)) / 2
+    lo_h = Fraction(math.ulp(math.nextafter(y, 0.0))) / 2  # below a power of two the ulp halves
+    return (fy - lo_h) ** 2 < fv < (fy + h) ** 2
+
+
+def test_derived_stats_textbook_values():
+    """AVG, sample VAR and sample STDDEV (the aggregates Sec. I reduces to
+    SUM) against the textbook definitions in exact rationals (the
+    statistics module), on groups whose sums make every IEEE step exact."""
+    import statistics
+
+    groups = [[1.0, 2.0, 3.0, 4.0, 5.0], [2.0, 4.0, 4.0, 4.0, 5.0, 5.0, 7.0, 9.0], [-3.0, 3.0],
+              [0.5, 0.25, 0.75, 1.5], [10.0, 10.0, 10.0]]
+    s = [float(sum(g)) for g in groups]
+    q = [float(sum(x * x for x in g)) for g in groups]
+    c = [len(g) for g in groups]
+    avg, var, sd = O.derive_stats(s, q, c)
+    for i, g in enumerate(groups):
+        assert avg[i] == statistics.mean(g)
+        assert var[i] == float(statistics.variance([Fraction(x) for x in g]))  # sample variance, exact
+        assert _rne_sqrt_ok(var[i], sd[i])
+    assert var[1] == 32.0 / 7.0 and avg[1] == 5.0  # population variance would be 4.0
+    assert sd[4] == 0.0 and var[4] == 0.0
+
+
+def test_derived_stats_empty_and_single_row_groups():
+    avg, var, sd = O.derive_stats([0.0, 7.5, 3.0], [0.0, 56.25, 5.0], [0, 1, 2])
+    assert np.isnan(avg[0]) and np.isnan(var[0]) and np.isnan(sd[0])
+    assert avg[1] == 7.5 and np.isnan(var[1]) and np.isnan(sd[1])
+    assert avg[2] == 1.5 and var[2] == 0.5 and _rne_sqrt_ok(0.5, sd[2])
+
+
+def test_derived_stats_square_root_correctly_rounded_and_variance_error():
+    """On general sums the sample variance stays within the error of the
+    fixed sequence (four roundings over the cancelling terms), and STDDEV is
+    the correctly rounded root of the variance (checked in exact rationals,
+    independent of the C library)."""
+    rng = np.random.default_rng(77)
+    G = 400
+    c = rng.integers(2, 10_000, G)
+    s = np.ldexp(rng.standard_normal(G), rng.integers(-20, 20, G))
+    q = (s * s) / c * (1.0 + rng.uniform(0.0, 3.0, G))  # q >= s^2/c: a variance >= 0
+    avg, var, sd = O.derive_stats(s, q, c)
+    eps = Fraction(1, 2 ** 53)
+    for g in range(G):
+        S, Q, C = Fraction(float(s[g])), Fraction(float(q[g])), int(c[g])
+        exact_m = S / C
+        exact_v = (Q - S * exact_m) / (C - 1)
+        assert abs(Fraction(float(avg[g])) - exact_m) <= abs(exact_m) * eps
+        bound = 4 * eps * (Q + abs(S * exact_m)) / (C - 1) * (1 + 8 * eps)
+        assert abs(Fraction(float(var[g])) - exact_v) <= bound
+        if var[g] >= 0:
+            assert _rne_sqrt_ok(float(var[g]), float(sd[g]))
+        else:
+            assert np.isnan(sd[g])
