@@ -390,6 +390,32 @@ int repro_profile_read(float* ms, int cap, int* count);
 /* Library version string. */
 const char* repro_version(void);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * GroupBy-SUM as repro_groupby_sum, with the same arguments, status bits and
+ * result bits, but with no workspace argument.  Its scratch memory is a
+ * static device array of REPRO_NOALLOC_SCRATCH_BYTES inside the library;
+ * every GPU the library runs on holds its own copy until the process ends.
+ * The call allocates nothing (no hipMalloc, no hipFree).
+ *
+ *   - REPRO_EINVAL when repro_workspace_bytes(...) for these sizes exceeds
+ *     REPRO_NOALLOC_SCRATCH_BYTES (it covers every call whose groups fit one
+ *     workgroup's LDS up to 2^31 rows, and small high-cardinality calls),
+ *     and for every argument repro_groupby_sum rejects.
+ *   - The scratch array belongs to the device that is current on the calling
+ *     thread; `stream` must belong to that device.  Its address is looked up
+ *     once per device (REPRO_EHIP if that fails).
+ *   - All calls on one GPU share that GPU's array and it keeps the last
+ *     call's contents: two calls that may overlap on one GPU (different
+ *     streams, or host threads without ordering) race on it and give wrong
+ *     results.  Order them on one stream or with events.
+ */
+#define REPRO_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int repro_groupby_sum_noalloc(const void* keys, repro_key_t kt, const void* values, repro_scalar_t vt, int64_t n,
+                              int64_t num_groups, repro_scalar_t T, int L, void* states, uint32_t* status,
+                              hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,6 +34,7 @@ class BatchConfig(ctypes.Structure):
 
 
 MAX_COLS, MAX_AGGS = 8, 4
+NOALLOC_SCRATCH_BYTES = 64 << 20  # REPRO_NOALLOC_SCRATCH_BYTES
 
 
 class Query(ctypes.Structure):
@@ -125,6 +126,8 @@ def load():
     lib.repro_groupby_sum_cols.argtypes = [vp, i32, i32, vp, vp, i64, i64, i32, i32, vp, vp, sz, vp, vp]
     lib.repro_plain_groupby_sum_cols.restype = ctypes.c_int
     lib.repro_plain_groupby_sum_cols.argtypes = [vp, i32, i32, vp, vp, i64, i64, vp, vp, vp]
+    lib.repro_groupby_sum_noalloc.restype = ctypes.c_int
+    lib.repro_groupby_sum_noalloc.argtypes = [vp, i32, vp, i32, i64, i64, i32, i32, vp, vp, vp]
     lib.repro_version.restype = ctypes.c_char_p
     lib.repro_version.argtypes = []
     for name in ("repro_state_init", "repro_groupby_sum", "repro_merge", "repro_finalize",

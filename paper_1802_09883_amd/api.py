@@ -112,6 +112,34 @@ def groupby_sum(keys: torch.Tensor, values: torch.Tensor, num_groups: int, L: in
     return states
 
 
+def groupby_sum_noalloc(keys: torch.Tensor, values: torch.Tensor, num_groups: int, L: int = 2, T=torch.float64,
+                       states: torch.Tensor | None = None, status: torch.Tensor | None = None,
+                       stream=None) -> torch.Tensor:
+    """``groupby_sum`` through the entry point that allocates nothing: its
+    scratch memory is the library's static device array, shared by every call
+    on the GPU (calls that may overlap on one GPU race).  ``states`` must be
+    given where the caller cannot allocate (a fresh state buffer is made
+    otherwise)."""
+    lib = _lib.load()
+    if keys.dtype not in _KEY or values.dtype not in _SCALAR:
+        raise TypeError("keys int32/int64, values float32/float64")
+    if keys.shape != values.shape or keys.dim() != 1:
+        raise ValueError("keys and values must be 1-D of equal length")
+    if not (keys.is_cuda and values.is_cuda) or keys.device != values.device:
+        raise ValueError("keys and values must be on the same GPU")
+    if not (keys.is_contiguous() and values.is_contiguous()):
+        raise ValueError("keys and values must be contiguous")
+    dev = keys.device
+    if states is None:
+        states = state_init(num_groups, L, T, dev, stream)
+    with torch.cuda.device(dev):
+        rc = lib.repro_groupby_sum_noalloc(_vp(keys), _KEY[keys.dtype], _vp(values), _SCALAR[values.dtype],
+                                           keys.numel(), num_groups, _T(T), L, _vp(states), _vp(status),
+                                           _stream(dev, stream))
+    _lib.check(rc, "groupby_sum_noalloc")
+    return states
+
+
 def workspace_bytes_cols(n: int, num_groups: int, key_dtype, value_dtypes, L: int = 2, T=torch.float64) -> int:
     vts = (ctypes.c_int * len(value_dtypes))(*[_SCALAR[d] for d in value_dtypes])
     return int(_lib.load().repro_workspace_bytes_cols(n, num_groups, _KEY[key_dtype], len(value_dtypes), vts,

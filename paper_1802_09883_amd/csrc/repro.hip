@@ -22,6 +22,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "repro.h"
 #include "repro_device.hpp"
@@ -822,6 +823,35 @@ int run_plain(const void* keys, const void* values, int64_t n, int G, double* ou
 
 }  // namespace
 
+// ------------------------------------------- allocation-free entry point
+//
+// repro_groupby_sum_noalloc runs the planned kernels of repro_groupby_sum on
+// this static device array instead of a caller workspace.  In host code the
+// name `scratch` is only a host-side stand-in: the array's device address is
+// looked up once per device with hipGetSymbolAddress and that pointer is
+// what the kernels get.
+static __device__ __align__(256) unsigned char scratch[REPRO_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch`.
+int scratch_of_current_device(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return REPRO_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return REPRO_EHIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return REPRO_OK;
+}
+}  // namespace
+
 // ============================================================== C ABI
 
 extern "C" {
@@ -914,5 +944,24 @@ int repro_profile_read(float* ms, int cap, int* count) {
 }
 
 const char* repro_version(void) { return "librepro 0.1 (gfx950)"; }
+
+int repro_groupby_sum_noalloc(const void* keys, repro_key_t kt, const void* values, repro_scalar_t vt, int64_t n,
+                              int64_t num_groups, repro_scalar_t T, int L, void* states, uint32_t* status,
+                              hipStream_t stream) {
+    if (!valid_common(num_groups, T, L) || n < 0 || !states) return REPRO_EINVAL;
+    if (kt != REPRO_I32 && kt != REPRO_I64) return REPRO_EINVAL;
+    if (vt != REPRO_F32 && vt != REPRO_F64) return REPRO_EINVAL;
+    if (vt == REPRO_F64 && T == REPRO_F32) return REPRO_EINVAL;
+    if (n == 0) return REPRO_OK;
+    Plan p;
+    if (!make_plan(n, num_groups, L, T == REPRO_F64 ? Fmt<double>::JMAX : Fmt<float>::JMAX, scalar_size(vt), &p))
+        return REPRO_EINVAL;
+    if (p.ws > REPRO_NOALLOC_SCRATCH_BYTES) return REPRO_EINVAL;
+    void* ws = nullptr;
+    const int rc = scratch_of_current_device(&ws);
+    if (rc != REPRO_OK) return rc;
+    return repro_groupby_sum(keys, kt, values, vt, n, num_groups, T, L, states, ws, REPRO_NOALLOC_SCRATCH_BYTES,
+                             status, stream);
+}
 
 }  // extern "C"

@@ -66,6 +66,24 @@ def test_invalid_arguments_return_einval_without_gpu(lib):
     assert lib.repro_server_poll(null, None, None, 4, ctypes.byref(n), None, None, None) == _lib.REPRO_EINVAL
 
 
+def test_noalloc_entry_rejects_without_gpu(lib):
+    p = ctypes.c_void_p(0x1000)  # never dereferenced: checks fail first
+    null = ctypes.c_void_p(0)
+    # the arguments repro_groupby_sum rejects
+    assert lib.repro_groupby_sum_noalloc(p, 0, p, _lib.F64, 10, 4, _lib.F32, 2, p, null, null) == _lib.REPRO_EINVAL
+    assert lib.repro_groupby_sum_noalloc(p, 0, p, 1, 10, 4, 1, 5, p, null, null) == _lib.REPRO_EINVAL
+    assert lib.repro_groupby_sum_noalloc(p, 0, p, 1, 10, 4, 1, 2, null, null, null) == _lib.REPRO_EINVAL
+    # more scratch than the static array holds
+    n, G = 10_000_000, 1 << 22
+    assert lib.repro_workspace_bytes(n, G, _lib.I64, _lib.F64, _lib.F64, 2) > _lib.NOALLOC_SCRATCH_BYTES
+    assert lib.repro_groupby_sum_noalloc(p, 1, p, 1, n, G, 1, 2, p, null, null) == _lib.REPRO_EINVAL
+    # every LDS-path call up to 2^31 rows fits
+    for L, G in ((1, 7679), (2, 5484), (3, 4265), (4, 3489)):
+        assert 0 < lib.repro_workspace_bytes(1 << 31, G, _lib.I32, _lib.F64, _lib.F64, L) <= _lib.NOALLOC_SCRATCH_BYTES
+    # n = 0 is a no-op
+    assert lib.repro_groupby_sum_noalloc(null, 0, null, 1, 0, 4, 1, 2, p, null, null) == _lib.REPRO_OK
+
+
 def _jobs(specs):
     """Host job records with fake device addresses (the planner never
     dereferences them)."""
