@@ -102,9 +102,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (HBM counter calibration)")
+    ap.add_argument("--stream-ceiling", action="store_true",
+                    help="only measure the read-stream ceiling: a plain read kernel over the low-cardinality "
+                         "workload's bytes, swept over launch shapes")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
+    if args.stream_ceiling:
+        return stream_ceiling(args)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -174,8 +179,10 @@ def main():
         raise SystemExit(f"device status {int(status.item())} on a clean workload")
 
     log(f"timing {args.steps} steps")
-    ncol = 1 if fused else len(vts)  # aggregation launches per step
-    api.profile_arm(ncol * args.steps)
+    ncol = 1 if fused else len(vts)  # aggregation calls per step
+    # measured launches per call: the partitioned path reports its scatter and its aggregation
+    per_call = 2 if args.config == "highcard" else 1
+    api.profile_arm(ncol * per_call * args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -184,8 +191,9 @@ def main():
     t1 = time.perf_counter()
     kms = api.profile_read()
     ms_step = (t1 - t0) * 1000.0 / args.steps
-    kcol = [kms[i::ncol] for i in range(ncol)]
-    knames = ["+".join(name for name, _ in vts)] if fused else [name for name, _ in vts]
+    kcol = [kms[i::ncol * per_call] for i in range(ncol * per_call)]
+    knames = (["+".join(name for name, _ in vts)] if fused else [name for name, _ in vts]) if per_call == 1 \
+        else ["partition scatter", "partition aggregation"]
     log(f"step {ms_step:.3f} ms; aggregation kernel " +
         ", ".join(f"{name} {np.mean(k):.3f} ms" for name, k in zip(knames, kcol)))
 
@@ -242,9 +250,19 @@ def main():
                 "kernel_ms": round(k0, 4),
                 "alg_bytes_per_launch": alg_k0}
     if args.config == "highcard":
-        # the dominant cost is the whole partitioned pass: report it against the
-        # algorithmic bytes of the step rather than one kernel's share
-        roofline["note"] = "achieved uses the aggregation kernel alone; see step_hbm_frac for the whole path"
+        # the dominant kernel is the partition scatter: keys and values read
+        # once, (local key, value) pairs written once
+        vb = vts[0][1].element_size()
+        sc_bytes = n * (kb + vb) + n * (2 + vb)
+        sc_ms = float(np.mean(kcol[0]))
+        ag_ms = float(np.mean(kcol[1]))
+        sc_gbs = sc_bytes / (sc_ms * 1e-3) / 1e9
+        roofline.update({"achieved": round(sc_gbs, 1), "frac": round(sc_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                         "kernel": "k_part_scatter<int64,f64> (partition pass: key+value read, local key+value "
+                                   "written)", "kernel_ms": round(sc_ms, 4), "alg_bytes_per_launch": sc_bytes,
+                         "partition_aggregation": {"kernel": "k_agg_part<f64,f64,L=2>", "ms": round(ag_ms, 4),
+                                                   "alg_bytes": n * (2 + vb),
+                                                   "achieved": round(n * (2 + vb) / (ag_ms * 1e-3) / 1e9, 1)}})
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -395,12 +413,18 @@ def bench_sum(args):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     ms_dev = e0.elapsed_time(e1) / args.steps
-    pl = torch.zeros(1, dtype=torch.float64, device=dev)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        torch.sum(v, dim=0, out=pl[0])
+    # baseline: torch's (non-reproducible) sum reduction, device time by HIP
+    # events on the stream it runs on
+    for _ in range(args.warmup):
+        pl = torch.sum(v)
     torch.cuda.synchronize()
-    plain_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    p0.record()
+    for _ in range(args.steps):
+        pl = torch.sum(v)
+    p1.record()
+    torch.cuda.synchronize()
+    plain_ms = p0.elapsed_time(p1) / args.steps
     alg = n * 8
     ach = alg / (ms_dev * 1e-3) / 1e9
     cpu = None
@@ -413,8 +437,9 @@ def bench_sum(args):
         "config": {"workload": cfg["desc"].format(n=n, L=L), "name": "sum", "rows": n, "groups": 1, "L": L,
                    "parallelism": "single GPU"},
         "step_hbm_frac": round(ach / HBM_PEAK_GBS, 4),
-        "plain_fp64_atomic": {"ms_per_step": round(plain_ms, 4), "slowdown": round(ms / plain_ms, 3),
-                              "note": "torch.sum (non-reproducible tree reduction) on the same column"},
+        "plain_fp64_atomic": {"ms_per_step": round(plain_ms, 4), "slowdown": round(ms_dev / plain_ms, 3),
+                              "note": "torch.sum (non-reproducible tree reduction) on the same column; both "
+                                      "timed by HIP events on their stream"},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_sum<f64,f64,L=3> + k_sum_merge + state reset + finalize (whole step)",
@@ -526,7 +551,7 @@ def cpu_baseline_serve(pool, offs, rows, groups, seconds):
     from oracle import oracle
     from paper_1802_09883_amd import workloads
 
-    cores = max(1, min(16, os.cpu_count() or 1))
+    cores, host = host_cpus()
     t0 = time.perf_counter()
     done, nq = 0, 0
     for q, (n, G) in enumerate(zip(rows, groups)):
@@ -543,7 +568,7 @@ def cpu_baseline_serve(pool, offs, rows, groups, seconds):
         if time.perf_counter() - t0 > seconds:
             break
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "rows/s", "cores": cores, "kind": "oracle",
+    return {"value": done / dt, "unit": "rows/s", "cores": cores, "kind": "oracle", "host": host,
             "sample": f"first {nq} of {len(rows)} queries ({done} rows, 4 aggregates each), {cores} threads, "
                       f"{dt:.1f} s (key generation included)"}
 
@@ -553,7 +578,7 @@ def cpu_baseline_batched(specs, seconds):
     until about `seconds` of work, rows/s."""
     from oracle import oracle
 
-    cores = max(1, min(16, os.cpu_count() or 1))
+    cores, host = host_cpus()
     t0 = time.perf_counter()
     done, njobs = 0, 0
     for k, v, G, L in specs:
@@ -564,8 +589,48 @@ def cpu_baseline_batched(specs, seconds):
         if time.perf_counter() - t0 > seconds:
             break
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "rows/s", "cores": cores, "kind": "oracle",
+    return {"value": done / dt, "unit": "rows/s", "cores": cores, "kind": "oracle", "host": host,
             "sample": f"first {njobs} of {len(specs)} jobs ({done} rows), {cores} threads, {dt:.1f} s"}
+
+
+def stream_ceiling(args):
+    """Read-stream ceiling: repro_read_probe over 3.2e9 bytes (the keys and
+    both value columns of the low-cardinality scan), each launch shape timed
+    with HIP events over `steps` launches; prints one JSON line."""
+    import ctypes
+
+    import torch
+
+    from paper_1802_09883_amd import _lib
+
+    lib = _lib.load()
+    nbytes = CONFIGS["lowcard"]["rows"] * 16
+    dev = torch.device("cuda:0")
+    buf = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    sink = torch.zeros(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    shapes = [(wg, th) for th in (256, 512, 1024) for wg in (256, 512, 1024, 2048, 4096)]
+    res = []
+    for wg, th in shapes:
+        def launch():
+            _lib.check(lib.repro_read_probe(ctypes.c_void_p(buf.data_ptr()), nbytes, wg, th,
+                                            ctypes.c_void_p(sink.data_ptr()), ctypes.c_void_p(stream.cuda_stream)),
+                       "read_probe")
+        for _ in range(args.warmup):
+            launch()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            launch()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        res.append({"workgroups": wg, "threads": th, "ms": round(ms, 4), "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)})
+        log(f"read probe {wg} x {th}: {ms:.4f} ms, {res[-1]['GB/s']} GB/s")
+    best = max(res, key=lambda r: r["GB/s"])
+    agg_shape = next(r for r in res if r["workgroups"] == 256 and r["threads"] == 1024)
+    print(json.dumps({"metric": "read-stream ceiling", "bytes": nbytes, "steps": args.steps, "best": best,
+                      "aggregation_launch_shape": agg_shape, "peak_GB/s": HBM_PEAK_GBS, "sweep": res}), flush=True)
 
 
 def copy_calibration(nbytes):
@@ -581,12 +646,33 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 3}), flush=True)
 
 
+def host_cpus():
+    """Threads for the CPU baseline and a description of the host: every CPU
+    this process may run on (its affinity set), capped by OMP_NUM_THREADS
+    when the environment sets it (the job's share of a shared host)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cap = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    threads = max(1, min(avail, cap) if cap > 0 else avail)
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return threads, {"nproc": os.cpu_count(), "affinity": avail, "omp_num_threads": cap or None, "model": model}
+
+
 def cpu_baseline(keys, cols, G, L, seconds, T64=True):
     """The CPU oracle (threaded over row chunks, then merged) on a bounded
     prefix of the same rows, every column, finalised: rows/s."""
     from oracle import oracle
 
-    cores = max(1, min(16, os.cpu_count() or 1))
+    cores, host = host_cpus()
 
     def run(m):
         t0 = time.perf_counter()
@@ -605,7 +691,7 @@ def cpu_baseline(keys, cols, G, L, seconds, T64=True):
     for _ in range(reps):
         run(m)
     dt = time.perf_counter() - t0
-    return {"value": reps * m / dt, "unit": "rows/s", "cores": cores, "kind": "oracle",
+    return {"value": reps * m / dt, "unit": "rows/s", "cores": cores, "kind": "oracle", "host": host,
             "sample": f"{reps} pass(es) over the first {m} rows (of {len(keys)}) of all {len(cols)} column(s), "
                       f"{cores} threads, {dt:.1f} s"}
 

@@ -129,12 +129,23 @@ int repro_finalize(const void* states, int64_t num_groups, repro_scalar_t T, int
 
 /*
  * Baseline, NOT reproducible: out[g] += values[i] for keys[i] == g with
- * plain double-precision atomic adds (the built-in floating-point SUM the
- * paper compares against, Sec. VI).  out is double[num_groups], accumulated
- * into; status as above (bad keys and non-finite values are skipped).
+ * plain double-precision adds (the built-in floating-point SUM the paper
+ * compares against, Sec. VI).  out is double[num_groups], accumulated into;
+ * status as above (bad keys and non-finite values are skipped).
+ *
+ * Groups that fit one workgroup's LDS are summed with LDS double atomics,
+ * then one global atomic per group and workgroup.  Beyond that the same
+ * algorithm as the reproducible path runs on doubles (PartitionAndAggregate
+ * on built-in types, as Sec. VI-C compares): partition on the key's high
+ * bits, LDS double atomics per partition; this needs a workspace of
+ * repro_plain_workspace_bytes(...) bytes (256-byte aligned).  Without one
+ * (workspace NULL or too small), those groups take direct global double
+ * atomics instead.
  */
+size_t repro_plain_workspace_bytes(int64_t n, int64_t num_groups, repro_key_t kt, repro_scalar_t vt);
 int repro_plain_groupby_sum(const void* keys, repro_key_t kt, const void* values, repro_scalar_t vt, int64_t n,
-                            int64_t num_groups, double* out, uint32_t* status, hipStream_t stream);
+                            int64_t num_groups, double* out, void* workspace, size_t workspace_bytes,
+                            uint32_t* status, hipStream_t stream);
 
 /*
  * Several SUM aggregates over one GROUP BY (Sec. V-D: a query's aggregates
@@ -376,16 +387,29 @@ double repro_server_clock(void);
 int repro_server_destroy(repro_server* srv);
 
 /*
- * Profiling aid.  repro_profile_arm(k) makes the next k repro_groupby_sum
- * calls issued by the calling host thread record a pair of HIP events on
- * their stream, right before and right after the aggregation kernel (the
- * one pass over the rows).  repro_profile_read(ms, cap, &count) waits for
+ * Profiling aid.  repro_profile_arm(k) makes the next k measured launches
+ * of repro_groupby_sum calls issued by the calling host thread record a
+ * pair of HIP events on their stream, right before and right after the
+ * launch: the aggregation kernel (the one pass over the rows) on the LDS
+ * path; the partition scatter and then the partition aggregation (two
+ * measured launches per call) on the partitioned path.  The multi-column
+ * call measures its fused pass.  repro_profile_read(ms, cap, &count) waits for
  * the recorded events and writes the elapsed milliseconds of each measured
  * launch, in call order (at most cap), then disarms.  k <= 4096.  Events are
  * created on first use, per thread; no device memory is involved.
  */
 int repro_profile_arm(int max_launches);
 int repro_profile_read(float* ms, int cap, int* count);
+
+/*
+ * Measurement aid: reads `bytes` (a multiple of 16, 16-byte aligned device
+ * memory) once with 16-byte loads on a grid of `workgroups` x `threads`
+ * (threads a multiple of 64, at most 1024), folding the words so that the
+ * loads are kept; adds to *sink (device uint64) the number of workgroups
+ * that read nonzero data.  Its rate is the read-stream ceiling of the chip.
+ */
+int repro_read_probe(const void* data, size_t bytes, int workgroups, int threads, unsigned long long* sink,
+                     hipStream_t stream);
 
 /* Library version string. */
 const char* repro_version(void);

@@ -81,7 +81,9 @@ def load():
     lib.repro_groupby_sum.argtypes = [vp, i32, vp, i32, i64, i64, i32, i32, vp, vp, sz, vp, vp]
     lib.repro_merge.argtypes = [vp, vp, i64, i32, i32, vp]
     lib.repro_finalize.argtypes = [vp, i64, i32, i32, vp, vp]
-    lib.repro_plain_groupby_sum.argtypes = [vp, i32, vp, i32, i64, i64, vp, vp, vp]
+    lib.repro_plain_groupby_sum.argtypes = [vp, i32, vp, i32, i64, i64, vp, vp, sz, vp, vp]
+    lib.repro_plain_workspace_bytes.restype = sz
+    lib.repro_plain_workspace_bytes.argtypes = [i64, i64, i32, i32]
     lib.repro_profile_arm.argtypes = [i32]
     lib.repro_profile_arm.restype = ctypes.c_int
     lib.repro_profile_read.argtypes = [vp, i32, vp]
@@ -128,6 +130,8 @@ def load():
     lib.repro_plain_groupby_sum_cols.argtypes = [vp, i32, i32, vp, vp, i64, i64, vp, vp, vp]
     lib.repro_groupby_sum_noalloc.restype = ctypes.c_int
     lib.repro_groupby_sum_noalloc.argtypes = [vp, i32, vp, i32, i64, i64, i32, i32, vp, vp, vp]
+    lib.repro_read_probe.restype = ctypes.c_int
+    lib.repro_read_probe.argtypes = [vp, sz, i32, i32, vp, vp]
     lib.repro_version.restype = ctypes.c_char_p
     lib.repro_version.argtypes = []
     for name in ("repro_state_init", "repro_groupby_sum", "repro_merge", "repro_finalize",

@@ -289,13 +289,17 @@ def finalize(states: torch.Tensor, num_groups: int, L: int = 2, T=torch.float64,
 
 def plain_groupby_sum(keys: torch.Tensor, values: torch.Tensor, num_groups: int, out=None, status=None,
                       stream=None) -> torch.Tensor:
-    """Non-reproducible baseline: double-precision atomic GroupBy-SUM."""
+    """Non-reproducible baseline: double-precision GroupBy-SUM (LDS atomics;
+    partitioned first when the groups do not fit LDS, as the reproducible
+    path is)."""
     lib = _lib.load()
     keys, values = keys.contiguous(), values.contiguous()
     if out is None:
         out = _new(num_groups, torch.float64, keys.device, stream, zero=True)
+    need = int(lib.repro_plain_workspace_bytes(keys.numel(), num_groups, _KEY[keys.dtype], _SCALAR[values.dtype]))
+    ws = _workspace(need, keys.device, stream) if need else None
     rc = lib.repro_plain_groupby_sum(_vp(keys), _KEY[keys.dtype], _vp(values), _SCALAR[values.dtype], keys.numel(),
-                                     num_groups, _vp(out), _vp(status), _stream(keys.device, stream))
+                                     num_groups, _vp(out), _vp(ws), need, _vp(status), _stream(keys.device, stream))
     _lib.check(rc, "plain_groupby_sum")
     return out
 

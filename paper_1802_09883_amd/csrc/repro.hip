@@ -268,7 +268,7 @@ __device__ __forceinline__ int block_exclusive_scan(const int* cnt, int* off, in
 // (NaN/Inf/out of domain) keeps its slot with value +0.0, which contributes
 // nothing; its status bit is set.  The max-exponent step is left to the
 // aggregation of each partition, where the partition's tops sit in LDS.
-template <class KT, class VT, class AT, int RU>
+template <class KT, class VT, class AT, int RU, bool DOM = true>
 __global__ void __launch_bounds__(PART_BLOCK)
     k_part_scatter(const KT* __restrict__ keys, const VT* __restrict__ vals, int64_t n, int64_t G, int gp_shift, int F,
                    int64_t chunk, const long long* __restrict__ base, const int* __restrict__ rel,
@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(PART_BLOCK)
                 if (!finite_val(v)) {
                     err |= ERR_NONFINITE;
                     v = (VT)0;
-                } else if (v != (VT)0 && jreq_raw<AT>(frexp_raw(v)) > Fm::JMAX) {
+                } else if (DOM && v != (VT)0 && jreq_raw<AT>(frexp_raw(v)) > Fm::JMAX) {
                     err |= ERR_RANGE;
                     v = (VT)0;
                 }
@@ -392,6 +392,62 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_part(const uint16_t* __restri
         }
     }
     report(status, err);
+}
+
+// Baseline (NOT reproducible): the same partitioned pass on doubles (the
+// built-in type's PartitionAndAggregate the paper compares against).  One
+// work item's rows are summed into LDS doubles with atomic adds; a
+// partition taken by one item adds its sums to out directly, the items of
+// split partitions add theirs with global double atomics.
+constexpr int PLAIN_PART_BLOCK = 1024;
+template <class VT>
+__global__ void __launch_bounds__(PLAIN_PART_BLOCK)
+    k_agg_part_plain(const uint16_t* __restrict__ lkey, const VT* __restrict__ lval,
+                     const WorkItem* __restrict__ items, const int* __restrict__ nitems, int64_t G, int gp_shift,
+                     double* __restrict__ out) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* bins = reinterpret_cast<double*>(smem);
+    if ((int)blockIdx.x >= *nitems) return;  // uniform: the grid is an upper bound
+    const WorkItem it = items[blockIdx.x];
+    const int GP = 1 << gp_shift;
+    const int64_t g0 = (int64_t)it.p << gp_shift;
+    const int Gp = (int)min((int64_t)GP, G - g0);
+    for (int g = threadIdx.x; g < Gp; g += PLAIN_PART_BLOCK) bins[g] = 0.0;
+    __syncthreads();
+    // [r0, r1) is a whole number of 8-row groups starting on a multiple of 8
+    constexpr int VEC = 16 / sizeof(VT);
+    typedef typename VecT<VT, VEC>::type V;
+    typedef typename VecT<uint16_t, VEC>::type K;
+    constexpr int U = 4;  // vector loads in flight per thread
+    constexpr int64_t STEP = (int64_t)PLAIN_PART_BLOCK * VEC;
+    for (int64_t b = it.r0; b < it.r1; b += U * STEP) {
+        V x[U];
+        K kk[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t r = b + u * STEP + (int64_t)threadIdx.x * VEC;
+            if (r < it.r1) {
+                x[u] = *reinterpret_cast<const V*>(lval + r);
+                kk[u] = *reinterpret_cast<const K*>(lkey + r);
+            } else {
+                x[u] = (V)(VT)0;
+                kk[u] = (K)(uint16_t)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                if (x[u][e] != (VT)0) atomicAdd(&bins[kk[u][e]], (double)x[u][e]);
+    }
+    __syncthreads();
+    for (int g = threadIdx.x; g < Gp; g += PLAIN_PART_BLOCK) {
+        const double b = bins[g];
+        if (it.nchunks == 1)
+            out[g0 + g] += b;
+        else if (b != 0.0)
+            atomicAdd(&out[g0 + g], b);
+    }
 }
 
 // one thread per group of a split partition: fold its work items' partials
@@ -580,6 +636,26 @@ __global__ void __launch_bounds__(PLAIN_BLOCK) k_plain_global(const KT* __restri
     report(status, err);
 }
 
+// ------------------------------------------------ read-stream ceiling
+// Measurement aid: reads `words` 16-byte words once, grid-strided with four
+// loads in flight per thread, and folds them into one XOR per workgroup so
+// the loads are not removed.  Its rate is the read ceiling the aggregation
+// kernels are held against.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ void k_read_probe(const u32x4* __restrict__ p, size_t words, unsigned long long* __restrict__ sink) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    u32x4 acc = {0u, 0u, 0u, 0u};
+    for (; i + 3 * stride < words; i += 4 * stride) {
+        const u32x4 a = __builtin_nontemporal_load(p + i), b = __builtin_nontemporal_load(p + i + stride);
+        const u32x4 c = __builtin_nontemporal_load(p + i + 2 * stride), d = __builtin_nontemporal_load(p + i + 3 * stride);
+        acc ^= a ^ b ^ c ^ d;
+    }
+    for (; i < words; i += stride) acc ^= p[i];
+    const uint32_t any = wave_or((acc.x | acc.y | acc.z | acc.w) != 0u ? 1u : 0u);
+    if (any && threadIdx.x == 0) atomicAdd(sink, 1ull);
+}
+
 // ================================================================ host
 
 inline size_t scalar_size(repro_scalar_t t) { return t == REPRO_F64 ? 8 : 4; }
@@ -589,11 +665,15 @@ bool valid_common(int64_t G, repro_scalar_t T, int L) {
 }
 
 
-// High cardinality: partition, then aggregate every partition in LDS.
+// High cardinality: partition, then aggregate every partition in LDS.  A
+// partition holds 2^s groups, the largest power of two up to 2^smax whose
+// `gbytes` LDS bytes per group (plus one slot) fit the budget.  The plain
+// baseline (L = 0) keeps one double per group and no partials.
 bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
     p->path = 2;
-    int s = 12;
-    while (s > 6 && ((size_t)(1 << s) + 1) * (8 * L + 12) > LDS_BIN_BUDGET) --s;
+    const size_t gbytes = L > 0 ? (size_t)8 * L + 12 : 8;
+    int s = L > 0 ? 12 : 14;
+    while (s > 6 && ((size_t)(1 << s) + 1) * gbytes > LDS_BIN_BUDGET) --s;
     p->gp_shift = s;
     const int64_t F = (G + (1 << s) - 1) >> s;
     if (F > 4096) return false;  // cursors, counts and offsets of all partitions in LDS
@@ -607,7 +687,7 @@ bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
     const int64_t maxw = F + (n + (int64_t)PART_ALIGN * F + PART_CHUNK - 1) / PART_CHUNK;
     if (maxw > INT32_MAX / 2) return false;
     p->maxw = (int)maxw;
-    p->lds_agg2 = ((size_t)(1 << s) + 1) * (8 * L + 12);  // bins, TOP and P of aggregate_range
+    p->lds_agg2 = ((size_t)(1 << s) + 1) * gbytes;  // bins, TOP and P of aggregate_range (or plain bins)
     const int GP = 1 << s;
     size_t ws = 0;
     auto take = [&](size_t bytes) { size_t o = ws; ws += align_up(bytes, 256); return o; };
@@ -621,7 +701,7 @@ bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
     const size_t rows_pad = (size_t)n + (size_t)PART_ALIGN * F;  // partitions padded to 8 rows
     p->o_lkey = take(rows_pad * 2);
     p->o_lval = take(rows_pad * vsize);
-    p->o_ptop = take((size_t)maxw * GP * 4);
+    p->o_ptop = take(L > 0 ? (size_t)maxw * GP * 4 : 0);
     p->o_pK = take((size_t)maxw * GP * L * 8);
     p->ws = ws;
     return true;
@@ -668,6 +748,7 @@ int run_groupby_part(const void* keys, const void* values, int64_t n, int64_t G,
     hipLaunchKernelGGL(k_part_plan<VT>, dim3(1), dim3(PART_BLOCK), 0, st, size, p.F, PART_CHUNK, base, wfirst, items,
                        nitems, lkey, lval);
     LAUNCH_CHECK();
+    prof_before(st);
     if (p.sc_ru == 8)
         hipLaunchKernelGGL((k_part_scatter<KT, VT, AT, 8>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k, v, n, G,
                            p.gp_shift, p.F, p.chunk_hs, base, rel, lkey, lval, status);
@@ -675,6 +756,7 @@ int run_groupby_part(const void* keys, const void* values, int64_t n, int64_t G,
         hipLaunchKernelGGL((k_part_scatter<KT, VT, AT, 4>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k, v, n, G,
                            p.gp_shift, p.F, p.chunk_hs, base, rel, lkey, lval, status);
     LAUNCH_CHECK();
+    prof_after(st);
     prof_before(st);
     hipLaunchKernelGGL((k_agg_part<VT, AT, L>), dim3(p.maxw), dim3(AGG_BLOCK), p.lds_agg2, st, lkey, lval, items,
                        nitems, G, p.gp_shift, ptop, pK, S, C, status);
@@ -789,8 +871,61 @@ int state_op(int op, repro_scalar_t T, int L, void* a, const void* b, int64_t G,
     return T == REPRO_F64 ? state_op_L<double>(op, L, a, b, (int)G, st) : state_op_L<float>(op, L, a, b, (int)G, st);
 }
 
+// Plan of the partitioned baseline, or false (then global atomics).
+bool make_plan_plain(int64_t n, int64_t G, size_t vsize, Plan* p) {
+    memset(p, 0, sizeof(*p));
+    if ((size_t)G * 8 <= LDS_BIN_BUDGET) return false;
+    return make_plan_part(n, G, 0, vsize, p);
+}
+
 template <class KT, class VT>
-int run_plain(const void* keys, const void* values, int64_t n, int G, double* out, uint32_t* status, hipStream_t st) {
+int run_plain_part(const void* keys, const void* values, int64_t n, int64_t G, double* out, void* workspace,
+                   uint32_t* status, const Plan& p, hipStream_t st) {
+    unsigned char* ws = static_cast<unsigned char*>(workspace);
+    const KT* k = static_cast<const KT*>(keys);
+    const VT* v = static_cast<const VT*>(values);
+    int* counts = reinterpret_cast<int*>(ws + p.o_counts);
+    int* rel = reinterpret_cast<int*>(ws + p.o_rel);
+    long long* size = reinterpret_cast<long long*>(ws + p.o_size);
+    long long* base = reinterpret_cast<long long*>(ws + p.o_base);
+    int* wfirst = reinterpret_cast<int*>(ws + p.o_wfirst);
+    WorkItem* items = reinterpret_cast<WorkItem*>(ws + p.o_items);
+    int* nitems = reinterpret_cast<int*>(ws + p.o_nitems);
+    uint16_t* lkey = reinterpret_cast<uint16_t*>(ws + p.o_lkey);
+    VT* lval = reinterpret_cast<VT*>(ws + p.o_lval);
+    const size_t lds_h = (size_t)p.F * 4;
+    const void* scatter = p.sc_ru == 8 ? (const void*)k_part_scatter<KT, VT, double, 8, false>
+                                       : (const void*)k_part_scatter<KT, VT, double, 4, false>;
+    if (!allow_lds((const void*)k_part_hist<KT>, lds_h) || !allow_lds(scatter, p.lds_sc) ||
+        !allow_lds((const void*)k_agg_part_plain<VT>, p.lds_agg2))
+        return REPRO_EHIP;
+    hipLaunchKernelGGL(k_part_hist<KT>, dim3(p.nw), dim3(PART_BLOCK), lds_h, st, k, n, G, p.gp_shift, p.F, p.chunk_hs,
+                       counts);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_part_offsets, dim3(p.F), dim3(PART_WG), 0, st, counts, p.nw, p.F, rel, size);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_part_plan<VT>, dim3(1), dim3(PART_BLOCK), 0, st, size, p.F, PART_CHUNK, base, wfirst, items,
+                       nitems, lkey, lval);
+    LAUNCH_CHECK();
+    if (p.sc_ru == 8)
+        hipLaunchKernelGGL((k_part_scatter<KT, VT, double, 8, false>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k, v,
+                           n, G, p.gp_shift, p.F, p.chunk_hs, base, rel, lkey, lval, status);
+    else
+        hipLaunchKernelGGL((k_part_scatter<KT, VT, double, 4, false>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k, v,
+                           n, G, p.gp_shift, p.F, p.chunk_hs, base, rel, lkey, lval, status);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_agg_part_plain<VT>), dim3(p.maxw), dim3(PLAIN_PART_BLOCK), p.lds_agg2, st, lkey, lval, items,
+                       nitems, G, p.gp_shift, out);
+    LAUNCH_CHECK();
+    return REPRO_OK;
+}
+
+template <class KT, class VT>
+int run_plain(const void* keys, const void* values, int64_t n, int G, double* out, void* workspace,
+              size_t workspace_bytes, uint32_t* status, hipStream_t st) {
+    Plan pp;
+    if (make_plan_plain(n, G, sizeof(VT), &pp) && workspace && workspace_bytes >= pp.ws)
+        return run_plain_part<KT, VT>(keys, values, n, G, out, workspace, status, pp, st);
     const KT* k = static_cast<const KT*>(keys);
     const VT* v = static_cast<const VT*>(values);
     int64_t nwg = (n + 16 * PLAIN_TILE - 1) / (16 * PLAIN_TILE);
@@ -905,18 +1040,29 @@ int repro_finalize(const void* states, int64_t num_groups, repro_scalar_t T, int
     return state_op(2, T, L, out, states, num_groups, stream);
 }
 
+size_t repro_plain_workspace_bytes(int64_t n, int64_t num_groups, repro_key_t kt, repro_scalar_t vt) {
+    (void)kt;
+    if (num_groups < 1 || num_groups > INT32_MAX || n < 0 || (vt != REPRO_F32 && vt != REPRO_F64)) return 0;
+    Plan p;
+    return make_plan_plain(n, num_groups, scalar_size(vt), &p) ? p.ws : 0;
+}
+
 int repro_plain_groupby_sum(const void* keys, repro_key_t kt, const void* values, repro_scalar_t vt, int64_t n,
-                            int64_t num_groups, double* out, uint32_t* status, hipStream_t stream) {
+                            int64_t num_groups, double* out, void* workspace, size_t workspace_bytes,
+                            uint32_t* status, hipStream_t stream) {
     if (num_groups < 1 || num_groups > INT32_MAX || n < 0 || !out) return REPRO_EINVAL;
     if ((kt != REPRO_I32 && kt != REPRO_I64) || (vt != REPRO_F32 && vt != REPRO_F64)) return REPRO_EINVAL;
+    if (workspace && (uintptr_t)workspace % 256 != 0) return REPRO_EINVAL;
     if (n == 0) return REPRO_OK;
     if (!keys || !values) return REPRO_EINVAL;
     const int G = (int)num_groups;
+    void* ws = workspace;
+    const size_t wb = workspace_bytes;
     if (kt == REPRO_I32)
-        return vt == REPRO_F64 ? run_plain<int32_t, double>(keys, values, n, G, out, status, stream)
-                               : run_plain<int32_t, float>(keys, values, n, G, out, status, stream);
-    return vt == REPRO_F64 ? run_plain<int64_t, double>(keys, values, n, G, out, status, stream)
-                           : run_plain<int64_t, float>(keys, values, n, G, out, status, stream);
+        return vt == REPRO_F64 ? run_plain<int32_t, double>(keys, values, n, G, out, ws, wb, status, stream)
+                               : run_plain<int32_t, float>(keys, values, n, G, out, ws, wb, status, stream);
+    return vt == REPRO_F64 ? run_plain<int64_t, double>(keys, values, n, G, out, ws, wb, status, stream)
+                           : run_plain<int64_t, float>(keys, values, n, G, out, ws, wb, status, stream);
 }
 
 int repro_profile_arm(int max_launches) {
@@ -940,6 +1086,17 @@ int repro_profile_read(float* ms, int cap, int* count) {
     }
     *count = k;
     g_prof->armed = g_prof->used = 0;
+    return REPRO_OK;
+}
+
+int repro_read_probe(const void* data, size_t bytes, int workgroups, int threads, unsigned long long* sink,
+                     hipStream_t stream) {
+    if (!data || !sink || (uintptr_t)data % 16 != 0 || bytes % 16 != 0 || workgroups < 1 || threads < 64 ||
+        threads > 1024 || threads % 64 != 0)
+        return REPRO_EINVAL;
+    hipLaunchKernelGGL(k_read_probe, dim3(workgroups), dim3(threads), 0, stream, static_cast<const u32x4*>(data),
+                       bytes / 16, sink);
+    LAUNCH_CHECK();
     return REPRO_OK;
 }
 

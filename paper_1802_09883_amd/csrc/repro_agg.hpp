@@ -784,6 +784,104 @@ __device__ __forceinline__ void fold_into_state(const long long* K, int ks, int 
     }
 }
 
+// Hand-over of partial results between the workgroups of one launch (the
+// last one to finish merges the others'): the words are written with
+// device-scope stores, which go through to the point where every XCD sees
+// them; each thread waits for its stores to complete (published) before the
+// workgroup raises the arrival counter; the last workgroup reads them with
+// device-scope loads.  A device-wide __threadfence() would instead write
+// back the XCD's whole L2 once per workgroup, which costs microseconds each.
+template <class T>
+__device__ __forceinline__ void publish(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T collect(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void published() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no memory access moves across
+    __builtin_amdgcn_s_waitcnt(0);            // this thread's stores and atomics are complete
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Writes the canonical state of group g from (hi, lo) level words at top J,
+// and its finalised sum (equation of Sec. III-C) when `out` is given.
+template <class AT, int L>
+__device__ __forceinline__ void write_group(const long long* hi, const long long* lo, int J, AT* S, long long* C,
+                                            int G, int g, AT* out) {
+    typedef Fmt<AT> F;
+    AT q[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        long long cc, oo;
+        normalise<AT>(hi[l], lo[l], &cc, &oo);
+        S[(size_t)l * G + g] = make_S((AT*)0, F::B + (J - l) * F::W, oo);
+        C[(size_t)l * G + g] = cc;
+        if (out) {
+            const i128 K = (i128)cc * ((i128)1 << F::CARRY) + (i128)oo;
+            q[l] = round_exact<AT>(K, F::B + (J - l) * F::W - F::m);
+        }
+    }
+    if (out) {
+        AT acc = q[L - 1];
+#pragma unroll
+        for (int l = L - 2; l >= 0; --l) acc = acc + q[l];
+        out[g] = acc + (AT)0;
+    }
+}
+
+// Adds the level sums x[L] at top `top` to (hi, lo) words at top J >= top.
+template <class AT, int L>
+__device__ __forceinline__ void add_levels(const long long* x, int top, int J, long long* hi, long long* lo) {
+    constexpr int c = Fmt<AT>::CARRY;
+    const int d = J - top;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        long long v = 0;
+#pragma unroll
+        for (int q = 0; q < L; ++q) v = (q == l - d) ? x[q] : v;
+        hi[l] += v >> c;
+        lo[l] += v & ((1ll << c) - 1);
+    }
+}
+
+// Adds the spill words of one group (exact 128-bit units H * 2^64 + w per
+// absolute lattice index) kept at levels J - l, l < L, to (hi, lo).
+// The words are read with device-scope loads: other workgroups' atomics
+// may have updated them during the same launch (see publish above).
+template <class AT, int L>
+__device__ __forceinline__ void add_spill(const unsigned long long* sw, int J, long long* hi, long long* lo) {
+    constexpr int c = Fmt<AT>::CARRY;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const unsigned long long* w = sw + (size_t)(J - l) * 2;
+        const i128 T = (i128)(long long)collect(w + 1) * ((i128)1 << 64) + (i128)collect(w);
+        hi[l] += (long long)(T >> c);
+        lo[l] += (long long)(T & ((1ll << c) - 1));
+    }
+}
+
+// Starts (hi, lo) level words at top J from the caller's state of group g
+// (C into hi, the low part of S into lo, moved down by J - top), or from
+// the empty state when the job overwrites.  Returns nothing: J must already
+// include the state's top (state_top_of).
+template <class AT, int L>
+__device__ __forceinline__ void start_from_state(const AT* S, const long long* C, int G, int g, bool use, int J,
+                                                 long long* hi, long long* lo) {
+#pragma unroll
+    for (int l = 0; l < L; ++l) hi[l] = lo[l] = 0;
+    if (!use) return;
+    const int d = J - state_top(S[g]);
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        if (l - d >= 0) {
+            hi[l] = C[(size_t)(l - d) * G + g];
+            lo[l] = state_lo(S[(size_t)(l - d) * G + g]);
+        }
+    }
+}
+
 }  // namespace
 }  // namespace repro
 

@@ -98,81 +98,6 @@ __device__ __forceinline__ long long* C_ptr(void* st, int G, int L) {
     return reinterpret_cast<long long*>(static_cast<unsigned char*>(st) + align_up((size_t)G * L * sizeof(AT), 8));
 }
 
-// Writes the canonical state of group g from (hi, lo) level words at top J,
-// and its finalised sum (equation of Sec. III-C) when `out` is given.
-template <class AT, int L>
-__device__ __forceinline__ void write_group(const long long* hi, const long long* lo, int J, AT* S, long long* C,
-                                            int G, int g, AT* out) {
-    typedef Fmt<AT> F;
-    AT q[L];
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        long long cc, oo;
-        normalise<AT>(hi[l], lo[l], &cc, &oo);
-        S[(size_t)l * G + g] = make_S((AT*)0, F::B + (J - l) * F::W, oo);
-        C[(size_t)l * G + g] = cc;
-        if (out) {
-            const i128 K = (i128)cc * ((i128)1 << F::CARRY) + (i128)oo;
-            q[l] = round_exact<AT>(K, F::B + (J - l) * F::W - F::m);
-        }
-    }
-    if (out) {
-        AT acc = q[L - 1];
-#pragma unroll
-        for (int l = L - 2; l >= 0; --l) acc = acc + q[l];
-        out[g] = acc + (AT)0;
-    }
-}
-
-// Adds the level sums x[L] at top `top` to (hi, lo) words at top J >= top.
-template <class AT, int L>
-__device__ __forceinline__ void add_levels(const long long* x, int top, int J, long long* hi, long long* lo) {
-    constexpr int c = Fmt<AT>::CARRY;
-    const int d = J - top;
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        long long v = 0;
-#pragma unroll
-        for (int q = 0; q < L; ++q) v = (q == l - d) ? x[q] : v;
-        hi[l] += v >> c;
-        lo[l] += v & ((1ll << c) - 1);
-    }
-}
-
-// Adds the spill words of one group (exact 128-bit units H * 2^64 + w per
-// absolute lattice index) kept at levels J - l, l < L, to (hi, lo).
-template <class AT, int L>
-__device__ __forceinline__ void add_spill(const unsigned long long* sw, int J, long long* hi, long long* lo) {
-    constexpr int c = Fmt<AT>::CARRY;
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        const unsigned long long* w = sw + (size_t)(J - l) * 2;
-        const i128 T = (i128)(long long)w[1] * ((i128)1 << 64) + (i128)w[0];
-        hi[l] += (long long)(T >> c);
-        lo[l] += (long long)(T & ((1ll << c) - 1));
-    }
-}
-
-// Starts (hi, lo) level words at top J from the caller's state of group g
-// (C into hi, the low part of S into lo, moved down by J - top), or from
-// the empty state when the job overwrites.  Returns nothing: J must already
-// include the state's top (state_top_of).
-template <class AT, int L>
-__device__ __forceinline__ void start_from_state(const AT* S, const long long* C, int G, int g, bool use, int J,
-                                                 long long* hi, long long* lo) {
-#pragma unroll
-    for (int l = 0; l < L; ++l) hi[l] = lo[l] = 0;
-    if (!use) return;
-    const int d = J - state_top(S[g]);
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        if (l - d >= 0) {
-            hi[l] = C[(size_t)(l - d) * G + g];
-            lo[l] = state_lo(S[(size_t)(l - d) * G + g]);
-        }
-    }
-}
-
 template <class AT>
 __device__ __forceinline__ int state_top_of(const AT* S, int g, bool use, int L) {
     return use ? state_top(S[g]) : L - 1;
@@ -206,7 +131,10 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
         for (int l = 0; l < L; ++l) x[l] = bins[((size_t)l * (Gs + 1) + g) * R];
     };
     if (jb.nchunks == 1) {
-        if (EPOCH) __threadfence();  // this workgroup's spill atomics, read back below
+        if (EPOCH) {  // this workgroup's spill atomics, read back below
+            published();
+            __syncthreads();
+        }
         for (int g = tid; g < Gs; g += BATCH_BLOCK) {
             const int gg = (int)glo + g;
             long long x[L], hi[L], lo[L];
@@ -230,17 +158,16 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
         for (int g = tid; g < Gs; g += BATCH_BLOCK) {
             long long x[L];
             level_sums(g, x);
-            ptop[g] = TOP[g].x;
+            publish(&ptop[g], TOP[g].x);
 #pragma unroll
-            for (int l = 0; l < L; ++l) pK[(size_t)l * jb.gs + g] = x[l];
+            for (int l = 0; l < L; ++l) publish(&pK[(size_t)l * jb.gs + g], x[l]);
         }
     }
-    __threadfence();  // this thread's partial words visible device-wide before the count
+    published();  // this thread's partial words (and spill atomics) complete before the count
     __syncthreads();
     if (tid == 0) *s_last = (atomicAdd(&counters[jb.done_off + bi.slice], 1) == jb.nchunks - 1);
     __syncthreads();
     if (*s_last) {
-        __threadfence();  // see the other items' partials
         for (int g = tid; g < Gs; g += BATCH_BLOCK) {
             const int gg = (int)glo + g;
             long long hi[L], lo[L];
@@ -248,7 +175,7 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
             // unrolled: the loads of several chunks' partials in flight at once
 #pragma unroll 4
             for (int c = 0; c < jb.nchunks; ++c)
-                J = max(J, reinterpret_cast<const int*>(part0 + (size_t)c * pbytes)[g]);
+                J = max(J, collect(reinterpret_cast<const int*>(part0 + (size_t)c * pbytes) + g));
             start_from_state<AT, L>(S, C, jb.G, gg, jb.accumulate, J, hi, lo);
 #pragma unroll 4
             for (int c = 0; c < jb.nchunks; ++c) {
@@ -256,8 +183,8 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
                 const long long* pK = reinterpret_cast<const long long*>(pp + align_up((size_t)jb.gs * 4, 8));
                 long long x[L];
 #pragma unroll
-                for (int l = 0; l < L; ++l) x[l] = pK[(size_t)l * jb.gs + g];
-                add_levels<AT, L>(x, reinterpret_cast<const int*>(pp)[g], J, hi, lo);
+                for (int l = 0; l < L; ++l) x[l] = collect(&pK[(size_t)l * jb.gs + g]);
+                add_levels<AT, L>(x, collect(reinterpret_cast<const int*>(pp) + g), J, hi, lo);
             }
             if (EPOCH) add_spill<AT, L>(spill + (size_t)g * NJ * 2, J, hi, lo);
             write_group<AT, L>(hi, lo, J, S, C, jb.G, gg, out);

@@ -331,8 +331,8 @@ int repro_plain_groupby_sum_cols(const void* keys, repro_key_t kt, int ncols, co
             if (rc != REPRO_OK) return rc;
         } else {
             for (int i = c; i < c + std::max(nc, 1); ++i) {
-                const int rc = repro_plain_groupby_sum(keys, kt, values[i], vts[i], n, num_groups, outs[i], status,
-                                                       stream);
+                const int rc = repro_plain_groupby_sum(keys, kt, values[i], vts[i], n, num_groups, outs[i], nullptr,
+                                                       0, status, stream);
                 if (rc != REPRO_OK) return rc;
             }
         }

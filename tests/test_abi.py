@@ -84,6 +84,23 @@ def test_noalloc_entry_rejects_without_gpu(lib):
     assert lib.repro_groupby_sum_noalloc(null, 0, null, 1, 0, 4, 1, 2, p, null, null) == _lib.REPRO_OK
 
 
+def test_plain_baseline_workspace_and_probe_checks(lib):
+    # groups that fit LDS need no workspace; beyond, the partitioned baseline does
+    assert lib.repro_plain_workspace_bytes(10 ** 6, 1024, _lib.I32, _lib.F64) == 0
+    big = lib.repro_plain_workspace_bytes(10 ** 6, 1 << 22, _lib.I64, _lib.F64)
+    assert big >= 10 ** 6 * 10  # the partitioned (local key, value) columns
+    assert lib.repro_plain_workspace_bytes(10 ** 6, 0, _lib.I32, _lib.F64) == 0
+    p = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+    assert lib.repro_plain_groupby_sum(p, 0, p, 1, 10, 4, p, ctypes.c_void_p(0x1001), 1 << 20, null, null) == \
+        _lib.REPRO_EINVAL  # misaligned workspace
+    # the read probe rejects bad shapes before launching anything
+    assert lib.repro_read_probe(p, 1024, 0, 256, p, null) == _lib.REPRO_EINVAL
+    assert lib.repro_read_probe(p, 1024, 4, 100, p, null) == _lib.REPRO_EINVAL
+    assert lib.repro_read_probe(p, 1000, 4, 256, p, null) == _lib.REPRO_EINVAL
+    assert lib.repro_read_probe(null, 1024, 4, 256, p, null) == _lib.REPRO_EINVAL
+
+
 def _jobs(specs):
     """Host job records with fake device addresses (the planner never
     dereferences them)."""

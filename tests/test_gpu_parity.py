@@ -124,6 +124,24 @@ def test_largest_lds_group_count(L, extra):
     check_case(keys, vals, G, L, True, "largest LDS G" if extra == 0 else "one group beyond LDS")
 
 
+@pytest.mark.parametrize("G,tiles", [(1024, 64), (1024, 65), (1025, 8), (16, 256)])
+def test_merge_launch_limits(G, tiles):
+    """Few partials (partials x groups <= 2^16) are merged by one launch,
+    more by two; around that limit, and resumed from a state whose tops are
+    above the new rows'."""
+    rng = np.random.default_rng([G, tiles])
+    n = tiles * 8192
+    keys = rng.integers(0, G, n).astype(np.int32)
+    vals = np.ldexp(rng.standard_normal(n), rng.integers(-100, 100, n))
+    check_case(keys, vals, G, 2, True, f"merge launch limits G={G} tiles={tiles}")
+    big = np.ldexp(rng.standard_normal(G), rng.integers(300, 400, G))
+    orc, _ = O.groupby_sum(np.concatenate([np.arange(G, dtype=np.int32), keys]), np.concatenate([big, vals]), G, 2)
+    st, _ = gpu_groupby(np.arange(G, dtype=np.int32), big, G, 2)
+    st, status = gpu_groupby(keys, vals, G, 2, states=st)
+    assert status == 0
+    assert_same_states(st, orc, G, 2, True, "resumed from higher tops")
+
+
 def test_misaligned_columns_take_scalar_loads():
     keys, vals = WL.plain(n=50_001, salt=3)
     kt, vt = dev(keys), dev(vals)
@@ -310,6 +328,29 @@ def test_plain_baseline_close_to_exact():
     orc, _ = O.groupby_sum(keys, vals, 16, 3)
     ref = O.finalize(orc, 16, 3)
     scale = np.array([np.abs(vals[keys == g]).sum() for g in range(16)])
+    assert np.all(np.abs(out - ref) <= 1e-12 * scale)
+
+
+@pytest.mark.parametrize("G,kdt", [(100_003, np.int32), (1 << 22, np.int64)])
+def test_partitioned_plain_baseline_close_to_exact(G, kdt):
+    """The baseline for groups beyond LDS partitions first (the same
+    algorithm on doubles); its sums are within rounding of the exact ones,
+    bad keys and NaN rows are skipped and reported."""
+    rng = np.random.default_rng([G, 7])
+    n = 1_500_000
+    keys = rng.integers(-2, G + 2, n).astype(kdt)
+    vals = np.ldexp(rng.standard_normal(n), rng.integers(-30, 30, n))
+    vals[rng.random(n) < 1e-4] = np.nan
+    need = api._lib.load().repro_plain_workspace_bytes(n, G, 0 if kdt == np.int32 else 1, 1)
+    assert need > 0  # the partitioned baseline, not global atomics
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = api.plain_groupby_sum(dev(keys), dev(vals), G, status=status).cpu().numpy()
+    torch.cuda.synchronize()
+    orc, ost = O.groupby_sum(keys, vals, G, 3)
+    assert int(status.item()) == ost == (1 | 2)
+    ref = O.finalize(orc, G, 3)
+    ok = (keys >= 0) & (keys < G) & np.isfinite(vals)
+    scale = np.bincount(keys[ok].astype(np.int64), weights=np.abs(vals[ok]), minlength=G)
     assert np.all(np.abs(out - ref) <= 1e-12 * scale)
 
 
