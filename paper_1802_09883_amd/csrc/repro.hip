@@ -62,12 +62,13 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_lds(const KT* __restrict__ ke
                                                        int64_t n, int G, int R, int64_t chunk,
                                                        int* __restrict__ ptop, long long* __restrict__ pK,
                                                        unsigned long long* __restrict__ spill,
-                                                       uint32_t* __restrict__ status) {
+                                                       uint32_t* __restrict__ status, const int* __restrict__ seed) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ AggShared sh;
     const int64_t c0 = (int64_t)blockIdx.x * chunk;
     const int64_t c1 = (c0 + chunk < n) ? c0 + chunk : n;
-    const uint32_t err = aggregate_range<KT, VT, AT, L, VEC, true>(keys, vals, c0, c1, G, R, smem, sh, spill);
+    const uint32_t err =
+        aggregate_range<KT, VT, AT, L, VEC, true>(keys, vals, c0, c1, G, R, smem, sh, spill, 0, 0, seed);
     long long* bins = reinterpret_cast<long long*>(smem);
     const int2* TOP = reinterpret_cast<const int2*>(bins + (size_t)(G + 1) * R * L);
     fold_replicas<L, AGG_BLOCK>(bins, G, R);
@@ -79,6 +80,15 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_lds(const KT* __restrict__ ke
     report(status, err);
 }
 
+
+// Seed tops for k_agg_lds: one sampled tile per workgroup.
+template <class KT, class VT, class AT, int VEC>
+__global__ void __launch_bounds__(AGG_BLOCK) k_sample_lds(const KT* __restrict__ keys, const VT* __restrict__ vals,
+                                                          int64_t n, int G, int64_t stride, int* __restrict__ seed) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SrcCol<KT, VT, VEC, AGG_BLOCK> src(keys, vals);
+    sample_tops<SrcCol<KT, VT, VEC, AGG_BLOCK>, AT, AGG_BLOCK>(src, n, stride, G, reinterpret_cast<int*>(smem), seed);
+}
 
 // ------------------------------------------------- high cardinality path
 //
@@ -785,18 +795,29 @@ int run_groupby(const void* keys, const void* values, int64_t n, int64_t G64, vo
         !allow_lds((const void*)k_agg_lds<KT, VT, AT, L, 1>, p.lds))
         return REPRO_EHIP;
     unsigned long long* spill = reinterpret_cast<unsigned long long*>(ws + p.spill_off);
+    int* seed = p.seed_tiles ? reinterpret_cast<int*>(ws + p.seed_off) : nullptr;
     if (p.spill_used) {
-        hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(1024, (p.spill_words + 255) / 256)), dim3(256), 0,
-                           st, spill, p.spill_words);
+        hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(1024, (p.zero_words + 255) / 256)), dim3(256), 0,
+                           st, spill, p.zero_words);
+        LAUNCH_CHECK();
+    }
+    if (seed) {
+        const size_t lds_s = (size_t)(G + 1) * 4;
+        if (aligned)
+            hipLaunchKernelGGL((k_sample_lds<KT, VT, AT, VEC>), dim3(p.seed_tiles), dim3(AGG_BLOCK), lds_s, st, k, v, n,
+                               G, p.seed_stride, seed);
+        else
+            hipLaunchKernelGGL((k_sample_lds<KT, VT, AT, 1>), dim3(p.seed_tiles), dim3(AGG_BLOCK), lds_s, st, k, v, n,
+                               G, p.seed_stride, seed);
         LAUNCH_CHECK();
     }
     prof_before(st);
     if (aligned)
         hipLaunchKernelGGL((k_agg_lds<KT, VT, AT, L, VEC>), dim3(p.nwg), dim3(AGG_BLOCK), p.lds, st, k, v, n, G, p.R,
-                           p.chunk, ptop, pK, spill, status);
+                           p.chunk, ptop, pK, spill, status, seed);
     else
         hipLaunchKernelGGL((k_agg_lds<KT, VT, AT, L, 1>), dim3(p.nwg), dim3(AGG_BLOCK), p.lds, st, k, v, n, G, p.R,
-                           p.chunk, ptop, pK, spill, status);
+                           p.chunk, ptop, pK, spill, status, seed);
     LAUNCH_CHECK();
     prof_after(st);
     ColStates<AT> cs;

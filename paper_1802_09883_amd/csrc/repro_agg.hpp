@@ -52,13 +52,14 @@ struct VecT {
     typedef T type __attribute__((ext_vector_type(N)));
 };
 
-template <class T, int N>
+// NT: a non-temporal (streaming) load, for columns read once.
+template <class T, int N, bool NT = true>
 __device__ __forceinline__ void vload(const T* __restrict__ p, T* out) {
     if constexpr (N == 1) {
-        out[0] = *p;
+        out[0] = NT ? __builtin_nontemporal_load(p) : *p;
     } else {
         typedef typename VecT<T, N>::type V;
-        const V x = *reinterpret_cast<const V*>(p);
+        const V x = NT ? __builtin_nontemporal_load(reinterpret_cast<const V*>(p)) : *reinterpret_cast<const V*>(p);
 #pragma unroll
         for (int i = 0; i < N; ++i) out[i] = x[i];
     }
@@ -69,7 +70,7 @@ __device__ __forceinline__ void vload(const T* __restrict__ p, T* out) {
 // (u*BLOCK + tid)*VEC, so each vector load instruction of a wave reads one
 // contiguous span (the tile base is uniform, the offsets are 32-bit).  Rows
 // at or beyond `end` are flagged out of range.
-template <class KT, class VT, int VEC, int BLOCK>
+template <class KT, class VT, int VEC, int BLOCK, bool NT = true>
 __device__ __forceinline__ uint32_t load_tile(const KT* __restrict__ keys, const VT* __restrict__ vals,
                                               int64_t base, int64_t end, KT* k, VT* v, const uint32_t* off) {
     constexpr int U = ROWS_PER_THREAD / VEC;
@@ -79,8 +80,8 @@ __device__ __forceinline__ uint32_t load_tile(const KT* __restrict__ keys, const
     if (base + (int64_t)BLOCK * ROWS_PER_THREAD <= end) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            vload<KT, VEC>(kb + off[u], k + u * VEC);
-            vload<VT, VEC>(vb + off[u], v + u * VEC);
+            vload<KT, VEC, NT>(kb + off[u], k + u * VEC);
+            vload<VT, VEC, NT>(vb + off[u], v + u * VEC);
         }
         inr = (1u << ROWS_PER_THREAD) - 1;
     } else {
@@ -309,7 +310,7 @@ __device__ __forceinline__ void spill_row(unsigned long long* __restrict__ spill
 // accumulator type AT.
 
 // One value column: virtual row i is row i of the thread's rows.
-template <class KT, class VT, int VEC, int BLOCK>
+template <class KT, class VT, int VEC, int BLOCK, bool NT = true>
 struct SrcCol {
     static constexpr int RPT = ROWS_PER_THREAD;  // rows per thread and tile
     static constexpr int NR = RPT;               // virtual rows per thread and tile
@@ -326,7 +327,7 @@ struct SrcCol {
         for (int u = 0; u < RPT / VEC; ++u) off[u] = (uint32_t)((u * BLOCK + threadIdx.x) * VEC);
     }
     __device__ __forceinline__ uint32_t load(Buf& b, int64_t base, int64_t end) const {
-        return load_tile<KT, VT, VEC, BLOCK>(keys, vals, base, end, b.k, b.v, off);
+        return load_tile<KT, VT, VEC, BLOCK, NT>(keys, vals, base, end, b.k, b.v, off);
     }
     template <bool FULL, bool SLICE, class AT>
     __device__ __forceinline__ void classify(const Buf& b, uint32_t inr, int G, int* gi, int* ji, bool& clean,
@@ -376,7 +377,7 @@ struct SrcCols {
 #pragma unroll
             for (int u = 0; u < RPT / VEC; ++u) {
                 VT x[VEC];
-                vload<VT, VEC>(vb + off[u], x);
+                vload<VT, VEC, true>(vb + off[u], x);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) out[u * VEC + e] = (AT)x[e];
             }
@@ -394,7 +395,7 @@ struct SrcCols {
         uint32_t inr = 0;
         if (full) {
 #pragma unroll
-            for (int u = 0; u < RPT / VEC; ++u) vload<KT, VEC>(kb + off[u], b.k + u * VEC);
+            for (int u = 0; u < RPT / VEC; ++u) vload<KT, VEC, true>(kb + off[u], b.k + u * VEC);
             inr = (1u << RPT) - 1;
         } else {
 #pragma unroll
@@ -457,7 +458,8 @@ constexpr int QUIET_TILES = 1;   // quiet per-tile synchronisations before epoch
 template <class Src, class AT, int L, bool EPOCH, bool SLICE, int BLOCK>
 __device__ __forceinline__ uint32_t aggregate_src(const Src& src, int64_t c0, int64_t c1, int G, int R,
                                                   unsigned char* smem, AggShared& sh,
-                                                  unsigned long long* __restrict__ spill, int64_t glo, int64_t Gfull) {
+                                                  unsigned long long* __restrict__ spill, int64_t glo, int64_t Gfull,
+                                                  const int* __restrict__ seed = nullptr) {
     constexpr int TILE = Src::TILE;  // rows of one tile
     constexpr int NR = Src::NR;      // virtual rows per thread and tile
     typedef Fmt<AT> F;
@@ -473,15 +475,19 @@ __device__ __forceinline__ uint32_t aggregate_src(const Src& src, int64_t c0, in
     const uint32_t lane_off = (uint32_t)(rep * 8);
     for (int i = tid; i < (G + 1) * R * L; i += BLOCK) bins[i] = 0;
     const uint32_t h_init = extractor_hi_of((AT*)0, L - 1);
+    int tmax = L - 1;  // largest seeded top of this thread's groups
     for (int i = tid; i < G; i += BLOCK) {
-        TOP[i] = make_int2(L - 1, (int)h_init);
-        P[i] = L - 1;
+        int t = L - 1;
+        if (EPOCH && seed) t = min(max(t, seed[i]), F::JMAX);
+        TOP[i] = make_int2(t, t == L - 1 ? (int)h_init : (int)extractor_hi_of((AT*)0, t));
+        P[i] = t;
+        tmax = max(tmax, t);
     }
     if (tid == 0) {
         TOP[G] = make_int2(F::JMAX, (int)extractor_hi_of((AT*)0, F::JMAX));  // trash slot: never raised
         P[G] = F::JMAX;
         sh.newmax = L - 1;
-        sh.cnt = G;
+        sh.cnt = (EPOCH && seed) ? 0 : G;
         for (int q = 0; q < 3; ++q) sh.flag[q] = sh.spills[q] = sh.nraised[q] = 0;
     }
     __syncthreads();
@@ -494,6 +500,20 @@ __device__ __forceinline__ uint32_t aggregate_src(const Src& src, int64_t c0, in
     int epoch_left = 0;  // tiles left in the current epoch (0: per-tile mode)
     int quiet = 0;     // consecutive per-tile synchronisations without a raise
     bool ahead = false;  // this tile's tops were raised at the previous synchronisation
+    if (EPOCH && seed) {
+        // seeded tops: whether they are all equal, then straight into epoch mode
+        atomicMax(&sh.newmax, tmax);
+        __syncthreads();
+        const int nm = sh.newmax;
+        int c = 0;
+        for (int g = tid; g < G; g += BLOCK) c += (TOP[g].x == nm);
+        if (c) atomicAdd(&sh.cnt, c);
+        __syncthreads();
+        uni = (sh.cnt == G);
+        Ju = nm;
+        hu = extractor_hi_of((AT*)0, Ju);
+        epoch_left = EPOCH_TILES;
+    }
 
     // Per-tile mode: when many lanes of a wave deposit into one group (skewed
     // keys), that "hot" group (wave-uniform) is summed in registers and added
@@ -695,15 +715,29 @@ __device__ __forceinline__ uint32_t aggregate_src(const Src& src, int64_t c0, in
         if constexpr (EPOCH && !SLICE) {
             // branch-free: skipped rows (errors; their units are arbitrary)
             // add into the trash slot G, which is never read, so the rows'
-            // extraction chains can interleave
+            // extraction chains can interleave.  With one top for every group
+            // the extractors are workgroup-uniform (scalar registers).
+            if (uni) {
+                const uint32_t hs = __builtin_amdgcn_readfirstlane(hu);
 #pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                long long k[L];
-                extract_from_hi<L>(src.template value<AT>(bc, i), hi_[i], k);
-                unsigned char* w = smem + __umul24((uint32_t)gi[i], gstride) + lane_off;
+                for (int i = 0; i < NR; ++i) {
+                    long long k[L];
+                    extract_from_hi<L>(src.template value<AT>(bc, i), hs, k);
+                    unsigned char* w = smem + __umul24((uint32_t)gi[i], gstride) + lane_off;
 #pragma unroll
-                for (int l = 0; l < L; ++l)
-                    atomicAdd(reinterpret_cast<unsigned long long*>(w + l * lstride), (unsigned long long)k[l]);
+                    for (int l = 0; l < L; ++l)
+                        atomicAdd(reinterpret_cast<unsigned long long*>(w + l * lstride), (unsigned long long)k[l]);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < NR; ++i) {
+                    long long k[L];
+                    extract_from_hi<L>(src.template value<AT>(bc, i), hi_[i], k);
+                    unsigned char* w = smem + __umul24((uint32_t)gi[i], gstride) + lane_off;
+#pragma unroll
+                    for (int l = 0; l < L; ++l)
+                        atomicAdd(reinterpret_cast<unsigned long long*>(w + l * lstride), (unsigned long long)k[l]);
+                }
             }
         } else {
         // skipped rows (trash slot G: errors, and in slice mode the rows of
@@ -744,14 +778,43 @@ __device__ __forceinline__ uint32_t aggregate_src(const Src& src, int64_t c0, in
 }
 
 // One value column (the row source SrcCol).
-template <class KT, class VT, class AT, int L, int VEC, bool EPOCH, bool SLICE = false, int BLOCK = AGG_BLOCK>
+template <class KT, class VT, class AT, int L, int VEC, bool EPOCH, bool SLICE = false, int BLOCK = AGG_BLOCK,
+          bool NT = true>
 __device__ __forceinline__ uint32_t aggregate_range(const KT* __restrict__ keys, const VT* __restrict__ vals,
                                                     int64_t c0, int64_t c1, int G, int R, unsigned char* smem,
                                                     AggShared& sh, unsigned long long* __restrict__ spill,
-                                                    int64_t glo = 0, int64_t Gfull = 0) {
-    const SrcCol<KT, VT, VEC, BLOCK> src(keys, vals);
-    return aggregate_src<SrcCol<KT, VT, VEC, BLOCK>, AT, L, EPOCH, SLICE, BLOCK>(src, c0, c1, G, R, smem, sh, spill,
-                                                                                 glo, Gfull);
+                                                    int64_t glo = 0, int64_t Gfull = 0,
+                                                    const int* __restrict__ seed = nullptr) {
+    typedef SrcCol<KT, VT, VEC, BLOCK, NT> Src;
+    const Src src(keys, vals);
+    return aggregate_src<Src, AT, L, EPOCH, SLICE, BLOCK>(src, c0, c1, G, R, smem, sh, spill, glo, Gfull, seed);
+}
+
+// Seed tops (epoch-mode launches over many tiles): one tile per workgroup,
+// spread evenly over the rows, raises seed[g] (zero-initialised) to the
+// largest required top of group g among its rows.  The aggregation then
+// starts every group at that top instead of its lowest one: any top between
+// the lowest and the final one gives the same bits (extraction at a higher
+// top and realignment agree), so only the number of synchronisations while
+// tops settle changes.
+template <class Src, class AT, int BLOCK>
+__device__ __forceinline__ void sample_tops(const Src& src, int64_t n, int64_t tile_stride, int G, int* lt,
+                                            int* __restrict__ seed) {
+    constexpr int NR = Src::NR;
+    for (int i = threadIdx.x; i <= G; i += BLOCK) lt[i] = 0;
+    __syncthreads();
+    typename Src::Buf b;
+    const int64_t base = (int64_t)blockIdx.x * tile_stride;
+    const uint32_t inr = src.load(b, base, n);
+    int gi[NR], ji[NR];
+    bool clean = true;
+    src.template classify<false, false, AT>(b, inr, G, gi, ji, clean, 0, 0);
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+        if (ji[i] > 0) atomicMax(&lt[gi[i]], ji[i]);  // error rows and zeros have ji = 0
+    __syncthreads();
+    for (int g = threadIdx.x; g < G; g += BLOCK)
+        if (lt[g] > 0) atomicMax(&seed[g], lt[g]);
 }
 
 // Folds a workgroup's aligned LDS level sums of group g (K[l * ks], top

@@ -117,7 +117,8 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
     const int R = jb.R;
     // epoch mode (unsliced jobs): rows above a frozen top go to the job's spill array
     unsigned long long* spill = EPOCH ? spill_area + jb.spill_off / 8 : nullptr;
-    const uint32_t err = aggregate_range<KT, VT, AT, L, VEC, EPOCH, true, BATCH_BLOCK>(
+    // temporal loads: the items of one chunk's group slices read the same rows
+    const uint32_t err = aggregate_range<KT, VT, AT, L, VEC, EPOCH, true, BATCH_BLOCK, false>(
         static_cast<const KT*>(jb.keys), static_cast<const VT*>(jb.vals), r0, r1, Gs, R, smem, sh, spill, glo,
         jb.G);
     long long* bins = reinterpret_cast<long long*>(smem);

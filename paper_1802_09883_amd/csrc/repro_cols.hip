@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_cols(const KT* __restrict__ k
                                                         int64_t n, int G, int R, int64_t chunk,
                                                         int* __restrict__ ptop, long long* __restrict__ pK,
                                                         unsigned long long* __restrict__ spill,
-                                                        uint32_t* __restrict__ status) {
+                                                        uint32_t* __restrict__ status, const int* __restrict__ seed) {
     typedef SrcCols<KT, double, NC, AGG_BLOCK> Src;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ AggShared sh;
@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_cols(const KT* __restrict__ k
     const int Gv = NC * G;
     const Src src(keys, vals.p, f32mask, G);
     const uint32_t err =
-        aggregate_src<Src, double, L, true, false, AGG_BLOCK>(src, c0, c1, Gv, R, smem, sh, spill, 0, 0);
+        aggregate_src<Src, double, L, true, false, AGG_BLOCK>(src, c0, c1, Gv, R, smem, sh, spill, 0, 0, seed);
     long long* bins = reinterpret_cast<long long*>(smem);
     const int2* TOP = reinterpret_cast<const int2*>(bins + (size_t)(Gv + 1) * R * L);
     fold_replicas<L, AGG_BLOCK>(bins, Gv, R);
@@ -61,6 +61,17 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_cols(const KT* __restrict__ k
         for (int l = 0; l < L; ++l) pK[((size_t)blockIdx.x * L + l) * Gv + g] = bins[((size_t)l * (Gv + 1) + g) * R];
     }
     report(status, err);
+}
+
+// Seed tops for k_agg_cols: one sampled tile per workgroup.
+template <class KT, int NC>
+__global__ void __launch_bounds__(AGG_BLOCK) k_sample_cols(const KT* __restrict__ keys, ColPtrs vals,
+                                                           uint32_t f32mask, int64_t n, int G, int64_t stride,
+                                                           int* __restrict__ seed) {
+    typedef SrcCols<KT, double, NC, AGG_BLOCK> Src;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Src src(keys, vals.p, f32mask, G);
+    sample_tops<Src, double, AGG_BLOCK>(src, n, stride, NC * G, reinterpret_cast<int*>(smem), seed);
 }
 
 // Plain double atomics per column (LDS-privatised), the baseline.
@@ -155,14 +166,20 @@ int run_cols(const KT* keys, const void* const* values, uint32_t f32mask, int64_
     int* ptop = reinterpret_cast<int*>(ws);
     long long* pK = reinterpret_cast<long long*>(ws + align_up((size_t)p.nwg * Gv * 4, 256));
     unsigned long long* spill = reinterpret_cast<unsigned long long*>(ws + p.spill_off);
+    int* seed = p.seed_tiles ? reinterpret_cast<int*>(ws + p.seed_off) : nullptr;
     if (p.spill_used) {
-        hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(1024, (p.spill_words + 255) / 256)), dim3(256), 0,
-                           st, spill, p.spill_words);
+        hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>(1024, (p.zero_words + 255) / 256)), dim3(256), 0,
+                           st, spill, p.zero_words);
+        LAUNCH_CHECK();
+    }
+    if (seed) {
+        hipLaunchKernelGGL((k_sample_cols<KT, NC>), dim3(p.seed_tiles), dim3(AGG_BLOCK), (size_t)(Gv + 1) * 4, st,
+                           keys, vp, f32mask, n, G, p.seed_stride, seed);
         LAUNCH_CHECK();
     }
     prof_before(st);
     hipLaunchKernelGGL((k_agg_cols<KT, L, NC>), dim3(p.nwg), dim3(AGG_BLOCK), p.lds, st, keys, vp, f32mask, n, G,
-                       p.R, p.chunk, ptop, pK, spill, status);
+                       p.R, p.chunk, ptop, pK, spill, status, seed);
     LAUNCH_CHECK();
     prof_after(st);
     return run_merge<double, L>(p, G, NC, ws, cs, st);

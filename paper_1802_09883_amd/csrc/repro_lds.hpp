@@ -10,6 +10,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "repro.h"
 #include "repro_agg.hpp"
 #include "repro_device.hpp"
@@ -49,6 +51,8 @@ __global__ void __launch_bounds__(256) k_zero(unsigned long long* __restrict__ p
 constexpr int M1_GROUPS = 64, M1_WAVES = 4;
 constexpr int M2_GROUPS = 16, M2_SLICES = 16;
 constexpr int64_t MERGE_DIRECT_MAX = 1 << 16;  // partials x groups merged by k_merge_l2 alone
+constexpr int SEED_TILES = 64;      // tiles sampled for seed tops
+constexpr int SEED_MIN_TILES = 8;   // tiles per workgroup from which sampling pays
 
 template <class AT, int L>
 __global__ void __launch_bounds__(M1_GROUPS* M1_WAVES)
@@ -236,6 +240,10 @@ struct Plan {
     int pb, nq;     // partials per level-1 merge block, level-1 results
     size_t spill_off, spill_words;  // spill array: G x (JMAX+1) x {w, H}
     bool spill_used;  // a workgroup takes more than one tile (epoch mode, and so spills, possible)
+    size_t zero_words;  // spill array and seed tops, cleared before the launch when spill_used
+    size_t seed_off;    // seed tops: int per bin group
+    int seed_tiles;     // tiles sampled for them (0: no sampling)
+    int64_t seed_stride;  // rows between sampled tiles
     size_t lds;     // dynamic LDS bytes
     size_t ws;      // workspace bytes
 };
@@ -275,6 +283,14 @@ inline bool make_plan_lds(int64_t n, int64_t Gv, int L, int jmax, int64_t tile, 
     // workgroup no row can spill, and the array is neither cleared nor read
     p->spill_used = chunk > tile;
     ws += align_up(p->spill_words * 8, 256);
+    // seed tops (one int per bin group), cleared together with the spill
+    // array; sampled when every workgroup streams many tiles
+    p->seed_off = ws;
+    ws += align_up((size_t)Gv * 4, 256);
+    p->zero_words = (ws - p->spill_off) / 8;
+    const int64_t ntiles = (n + tile - 1) / tile;
+    p->seed_tiles = (chunk >= SEED_MIN_TILES * tile) ? (int)std::min<int64_t>(SEED_TILES, ntiles) : 0;
+    p->seed_stride = p->seed_tiles ? (ntiles / p->seed_tiles) * tile : 0;
     p->ws = ws;
     return true;
 }
