@@ -346,19 +346,26 @@ struct SrcCol {
 
 // NC value columns over one key column: virtual row c * RPT + r is column
 // c of row r, deposited into bin group c * Gc + key (the bins hold NC * Gc
-// groups).  Column c holds floats where bit c of f32mask is set, doubles
-// otherwise; floats widen exactly when AT is double.  Rows are loaded two
-// at a time (8- or 16-byte loads); every column must be aligned to two of
-// its elements and the keys to two keys.
-template <class KT, class AT, int NC, int BLOCK>
+// groups).  Column c holds floats where bit c of the column mask is set,
+// doubles otherwise; floats widen exactly when AT is double.  The mask is a
+// compile-time constant FMC (floats stay 4 bytes in the registers of the
+// prefetched tile and widen when used), or FM_RUNTIME: then it is the
+// runtime f32mask and every value widens to double as it is loaded.  Rows
+// are loaded two at a time (8- or 16-byte loads); every column must be
+// aligned to two of its elements and the keys to two keys.
+constexpr uint32_t FM_RUNTIME = 0xffffffffu;
+
+template <class KT, class AT, int NC, int BLOCK, uint32_t FMC = FM_RUNTIME>
 struct SrcCols {
     static constexpr int RPT = 8 / NC >= 2 ? 8 / NC : 2;
     static constexpr int VEC = 2;
     static constexpr int NR = RPT * NC;
     static constexpr int TILE = BLOCK * RPT;
+    static constexpr bool CT = FMC != FM_RUNTIME;
     struct Buf {
         KT k[RPT];
-        AT v[NC][RPT];
+        double d[NC][RPT];  // double columns (every column when the mask is a runtime one)
+        float f[NC][RPT];   // float columns of a compile-time mask
     };
     const KT* keys;
     const void* vals[NC];
@@ -371,21 +378,23 @@ struct SrcCols {
 #pragma unroll
         for (int u = 0; u < RPT / VEC; ++u) off[u] = (uint32_t)((u * BLOCK + threadIdx.x) * VEC);
     }
-    template <class VT>
-    __device__ __forceinline__ void load_col(const VT* __restrict__ vb, AT* out, bool full, uint32_t lim) const {
+    // column c stored as float (compile-time masks only)
+    static constexpr bool stored_f32(int c) { return CT && ((FMC >> c) & 1u); }
+    template <class VT, class OT>
+    __device__ __forceinline__ void load_col(const VT* __restrict__ vb, OT* out, bool full, uint32_t lim) const {
         if (full) {
 #pragma unroll
             for (int u = 0; u < RPT / VEC; ++u) {
                 VT x[VEC];
                 vload<VT, VEC, true>(vb + off[u], x);
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) out[u * VEC + e] = (AT)x[e];
+                for (int e = 0; e < VEC; ++e) out[u * VEC + e] = (OT)x[e];
             }
         } else {
 #pragma unroll
             for (int u = 0; u < RPT / VEC; ++u)
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) out[u * VEC + e] = (off[u] + e < lim) ? (AT)vb[off[u] + e] : (AT)0;
+                for (int e = 0; e < VEC; ++e) out[u * VEC + e] = (off[u] + e < lim) ? (OT)vb[off[u] + e] : (OT)0;
         }
     }
     __device__ __forceinline__ uint32_t load(Buf& b, int64_t base, int64_t end) const {
@@ -410,10 +419,17 @@ struct SrcCols {
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            if ((f32mask >> c) & 1u)
-                load_col<float>(static_cast<const float*>(vals[c]) + base, b.v[c], full, lim);
-            else
-                load_col<double>(static_cast<const double*>(vals[c]) + base, b.v[c], full, lim);
+            if constexpr (CT) {
+                if (stored_f32(c))
+                    load_col<float, float>(static_cast<const float*>(vals[c]) + base, b.f[c], full, lim);
+                else
+                    load_col<double, double>(static_cast<const double*>(vals[c]) + base, b.d[c], full, lim);
+            } else {
+                if ((f32mask >> c) & 1u)
+                    load_col<float, double>(static_cast<const float*>(vals[c]) + base, b.d[c], full, lim);
+                else
+                    load_col<double, double>(static_cast<const double*>(vals[c]) + base, b.d[c], full, lim);
+            }
         }
         return inr;
     }
@@ -424,7 +440,10 @@ struct SrcCols {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             int gc[RPT], jc[RPT];
-            classify_rows<FULL, false, KT, AT, AT_, RPT>(b.k, b.v[c], inr, Gc, gc, jc, clean, 0, 0);
+            if (stored_f32(c))
+                classify_rows<FULL, false, KT, float, AT_, RPT>(b.k, b.f[c], inr, Gc, gc, jc, clean, 0, 0);
+            else
+                classify_rows<FULL, false, KT, double, AT_, RPT>(b.k, b.d[c], inr, Gc, gc, jc, clean, 0, 0);
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
                 gi[c * RPT + r] = gc[r] == Gc ? G : c * Gc + gc[r];  // skipped rows: the trash slot G = NC * Gc
@@ -436,12 +455,17 @@ struct SrcCols {
     __device__ __forceinline__ uint32_t errors(const Buf& b, uint32_t inr, int64_t) const {
         uint32_t e = 0;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) e |= error_bits<KT, AT, AT_, RPT>(b.k, b.v[c], inr, Gc);
+        for (int c = 0; c < NC; ++c) {
+            if (stored_f32(c))
+                e |= error_bits<KT, float, AT_, RPT>(b.k, b.f[c], inr, Gc);
+            else
+                e |= error_bits<KT, double, AT_, RPT>(b.k, b.d[c], inr, Gc);
+        }
         return e;
     }
     template <class AT_>
     __device__ __forceinline__ AT_ value(const Buf& b, int i) const {
-        return (AT_)b.v[i / RPT][i % RPT];
+        return stored_f32(i / RPT) ? (AT_)b.f[i / RPT][i % RPT] : (AT_)b.d[i / RPT][i % RPT];
     }
 };
 

@@ -37,13 +37,13 @@ struct ColPtrs {
     const void* p[COLS_FUSED_MAX];
 };
 
-template <class KT, int L, int NC>
+template <class KT, int L, int NC, uint32_t FMC>
 __global__ void __launch_bounds__(AGG_BLOCK) k_agg_cols(const KT* __restrict__ keys, ColPtrs vals, uint32_t f32mask,
                                                         int64_t n, int G, int R, int64_t chunk,
                                                         int* __restrict__ ptop, long long* __restrict__ pK,
                                                         unsigned long long* __restrict__ spill,
                                                         uint32_t* __restrict__ status, const int* __restrict__ seed) {
-    typedef SrcCols<KT, double, NC, AGG_BLOCK> Src;
+    typedef SrcCols<KT, double, NC, AGG_BLOCK, FMC> Src;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ AggShared sh;
     const int64_t c0 = (int64_t)blockIdx.x * chunk;
@@ -64,11 +64,11 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_cols(const KT* __restrict__ k
 }
 
 // Seed tops for k_agg_cols: one sampled tile per workgroup.
-template <class KT, int NC>
+template <class KT, int NC, uint32_t FMC>
 __global__ void __launch_bounds__(AGG_BLOCK) k_sample_cols(const KT* __restrict__ keys, ColPtrs vals,
                                                            uint32_t f32mask, int64_t n, int G, int64_t stride,
                                                            int* __restrict__ seed) {
-    typedef SrcCols<KT, double, NC, AGG_BLOCK> Src;
+    typedef SrcCols<KT, double, NC, AGG_BLOCK, FMC> Src;
     extern __shared__ __align__(16) unsigned char smem[];
     const Src src(keys, vals.p, f32mask, G);
     sample_tops<Src, double, AGG_BLOCK>(src, n, stride, NC * G, reinterpret_cast<int*>(smem), seed);
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(PLAIN_COLS_BLOCK)
             err |= (in && !kok) ? ERR_KEY : 0u;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                const double v = b.v[c][r];
+                const double v = src.template value<double>(b, c * Src::RPT + r);
                 const bool fin = finite_val(v);
                 err |= (in && !fin) ? ERR_NONFINITE : 0u;
                 if (in && kok && fin) atomicAdd(&bins[c * G + (int)b.k[r]], v);
@@ -149,11 +149,11 @@ inline bool cols_aligned(const void* keys, repro_key_t kt, const void* const* va
     return true;
 }
 
-template <class KT, int L, int NC>
+template <class KT, int L, int NC, uint32_t FMC>
 int run_cols(const KT* keys, const void* const* values, uint32_t f32mask, int64_t n, int G, void* const* states,
              unsigned char* ws, uint32_t* status, const Plan& p, hipStream_t st) {
     const int Gv = NC * G;
-    const void* fn = (const void*)k_agg_cols<KT, L, NC>;
+    const void* fn = (const void*)k_agg_cols<KT, L, NC, FMC>;
     if (!allow_lds(fn, p.lds)) return REPRO_EHIP;
     ColPtrs vp;
     ColStates<double> cs;
@@ -173,12 +173,12 @@ int run_cols(const KT* keys, const void* const* values, uint32_t f32mask, int64_
         LAUNCH_CHECK();
     }
     if (seed) {
-        hipLaunchKernelGGL((k_sample_cols<KT, NC>), dim3(p.seed_tiles), dim3(AGG_BLOCK), (size_t)(Gv + 1) * 4, st,
+        hipLaunchKernelGGL((k_sample_cols<KT, NC, FMC>), dim3(p.seed_tiles), dim3(AGG_BLOCK), (size_t)(Gv + 1) * 4, st,
                            keys, vp, f32mask, n, G, p.seed_stride, seed);
         LAUNCH_CHECK();
     }
     prof_before(st);
-    hipLaunchKernelGGL((k_agg_cols<KT, L, NC>), dim3(p.nwg), dim3(AGG_BLOCK), p.lds, st, keys, vp, f32mask, n, G,
+    hipLaunchKernelGGL((k_agg_cols<KT, L, NC, FMC>), dim3(p.nwg), dim3(AGG_BLOCK), p.lds, st, keys, vp, f32mask, n, G,
                        p.R, p.chunk, ptop, pK, spill, status, seed);
     LAUNCH_CHECK();
     prof_after(st);
@@ -189,10 +189,19 @@ template <class KT, int L>
 int dispatch_nc(int nc, const void* keys, const void* const* values, uint32_t f32mask, int64_t n, int G,
                 void* const* states, unsigned char* ws, uint32_t* status, const Plan& p, hipStream_t st) {
     const KT* k = static_cast<const KT*>(keys);
+    // two columns: the column types are compile-time (floats stay 4 bytes
+    // while prefetched); three or four: a runtime mask
+    if (nc == 2) {
+        switch (f32mask) {
+            case 0: return run_cols<KT, L, 2, 0u>(k, values, f32mask, n, G, states, ws, status, p, st);
+            case 1: return run_cols<KT, L, 2, 1u>(k, values, f32mask, n, G, states, ws, status, p, st);
+            case 2: return run_cols<KT, L, 2, 2u>(k, values, f32mask, n, G, states, ws, status, p, st);
+            default: return run_cols<KT, L, 2, 3u>(k, values, f32mask, n, G, states, ws, status, p, st);
+        }
+    }
     switch (nc) {
-        case 2: return run_cols<KT, L, 2>(k, values, f32mask, n, G, states, ws, status, p, st);
-        case 3: return run_cols<KT, L, 3>(k, values, f32mask, n, G, states, ws, status, p, st);
-        case 4: return run_cols<KT, L, 4>(k, values, f32mask, n, G, states, ws, status, p, st);
+        case 3: return run_cols<KT, L, 3, FM_RUNTIME>(k, values, f32mask, n, G, states, ws, status, p, st);
+        case 4: return run_cols<KT, L, 4, FM_RUNTIME>(k, values, f32mask, n, G, states, ws, status, p, st);
     }
     return REPRO_EINVAL;
 }

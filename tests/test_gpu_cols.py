@@ -85,6 +85,27 @@ def test_fused_widths_levels_keys(ncols, L, kdt):
     check_cols(keys, mixed_cols(n, ncols, [ncols, L, 7]), G, L, True, f"{ncols} cols fused")
 
 
+@pytest.mark.parametrize("mask", [0, 1, 2, 3])
+def test_two_column_type_combinations(mask):
+    """Every float/double combination of two fused columns (bit c of mask:
+    column c is float32), with subnormal, non-finite and out-of-domain values
+    and enough rows for the sampled seed tops and epoch mode."""
+    n = 2_000_003
+    rng = np.random.default_rng([mask, 5])
+    G = 500
+    keys = rng.integers(0, G, n).astype(np.int32)
+    cols = []
+    for c in range(2):
+        if (mask >> c) & 1:
+            v = np.ldexp(rng.standard_normal(n), rng.integers(-149, 120, n)).astype(np.float32)
+            v[rng.random(n) < 1e-4] = np.inf
+        else:
+            v = np.ldexp(rng.standard_normal(n), rng.integers(-1074, 1010, n))
+            v[rng.random(n) < 1e-4] = np.nan
+        cols.append(v)
+    check_cols(keys, cols, G, 3, True, f"two columns, float mask {mask}")
+
+
 @pytest.mark.parametrize("n", [1, 7, 4095, 4096, 4097, 8193])
 def test_fused_small_and_ragged(n):
     rng = np.random.default_rng(n)
