@@ -95,7 +95,11 @@ int repro_state_init(void* states, int64_t num_groups, repro_scalar_t T, int L, 
  *   values     float or double (vt).  vt = F32 with T = F64 widens exactly;
  *              vt = F64 with T = F32 is REPRO_EINVAL.
  *   n          rows, >= 0 (n = 0 enqueues nothing).
- *   num_groups 1 .. 2^31-1.
+ *   num_groups 1 .. 2^31-1.  Groups that do not fit one workgroup's LDS are
+ *              partitioned first (Alg. 4); beyond 2^24 groups (2^23 at
+ *              L = 4) a second partitioning level runs, and the call waits
+ *              once for its stream to read the first level's partition
+ *              sizes (so such calls cannot be captured in a HIP graph).
  *   L          levels, 1..4.
  *   workspace  >= repro_workspace_bytes(...) bytes, 256-byte aligned device
  *              memory (may be NULL if that size is 0); contents on entry are

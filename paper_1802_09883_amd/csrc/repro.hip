@@ -112,6 +112,7 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_sample_lds(const KT* __restrict__
 constexpr int PART_BLOCK = 1024;
 constexpr int PART_WG = 256;                  // histogram/scatter workgroups
 constexpr int64_t PART_CHUNK = 128 * 1024;    // rows per aggregation work item
+constexpr int DEEP_MAX_F = 1024;              // super-partitions of the second partitioning level
 
 struct WorkItem {
     int p;        // partition
@@ -278,11 +279,11 @@ __device__ __forceinline__ int block_exclusive_scan(const int* cnt, int* off, in
 // (NaN/Inf/out of domain) keeps its slot with value +0.0, which contributes
 // nothing; its status bit is set.  The max-exponent step is left to the
 // aggregation of each partition, where the partition's tops sit in LDS.
-template <class KT, class VT, class AT, int RU, bool DOM = true>
+template <class KT, class VT, class AT, int RU, bool DOM = true, class LK = uint16_t>
 __global__ void __launch_bounds__(PART_BLOCK)
     k_part_scatter(const KT* __restrict__ keys, const VT* __restrict__ vals, int64_t n, int64_t G, int gp_shift, int F,
                    int64_t chunk, const long long* __restrict__ base, const int* __restrict__ rel,
-                   uint16_t* __restrict__ lkey, VT* __restrict__ lval, uint32_t* __restrict__ status) {
+                   LK* __restrict__ lkey, VT* __restrict__ lval, uint32_t* __restrict__ status) {
     typedef Fmt<AT> Fm;
     constexpr int SC_TILE = RU * PART_BLOCK;  // RU rows per thread and tile
     extern __shared__ __align__(16) unsigned char smem[];
@@ -290,8 +291,8 @@ __global__ void __launch_bounds__(PART_BLOCK)
     int* cnt = reinterpret_cast<int*>(cur + F);                   // F: rows in this tile
     int* off = cnt + F;                                           // F: tile offsets
     VT* sv = reinterpret_cast<VT*>(off + F);                      // SC_TILE staged values
-    uint16_t* sk = reinterpret_cast<uint16_t*>(sv + SC_TILE);     // staged local keys
-    uint16_t* sp = sk + SC_TILE;                                  // staged partitions
+    LK* sk = reinterpret_cast<LK*>(sv + SC_TILE);                 // staged local keys
+    uint16_t* sp = reinterpret_cast<uint16_t*>(sk + SC_TILE);     // staged partitions
     __shared__ int wsum[PART_BLOCK / 64];
     const int t = threadIdx.x;
     for (int i = t; i < F; i += PART_BLOCK) cur[i] = base[i] + rel[(size_t)blockIdx.x * F + i];
@@ -304,7 +305,7 @@ __global__ void __launch_bounds__(PART_BLOCK)
         __syncthreads();
         int pi[RU], rk[RU];
         int64_t kk[RU];
-        uint16_t lk[RU];
+        LK lk[RU];
         VT vv[RU];
         // loads first, so that the memory requests of all rows overlap
 #pragma unroll
@@ -331,7 +332,7 @@ __global__ void __launch_bounds__(PART_BLOCK)
                 }
                 if ((uint64_t)key < (uint64_t)G) {
                     pi[u] = (int)(key >> gp_shift);
-                    lk[u] = (uint16_t)((uint32_t)key & gmask);
+                    lk[u] = (LK)((uint32_t)key & gmask);
                     vv[u] = v;
                     rk[u] = atomicAdd(&cnt[pi[u]], 1);
                 } else {
@@ -375,8 +376,8 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_part(const uint16_t* __restri
                                                         const WorkItem* __restrict__ items,
                                                         const int* __restrict__ nitems, int64_t G, int gp_shift,
                                                         int* __restrict__ ptop, long long* __restrict__ pK,
-                                                        AT* __restrict__ S, long long* __restrict__ C,
-                                                        uint32_t* __restrict__ status) {
+                                                        AT* __restrict__ S, long long* __restrict__ C, int64_t gbase,
+                                                        int64_t Gstride, uint32_t* __restrict__ status) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ AggShared sh;
     if ((int)blockIdx.x >= *nitems) return;  // uniform: the grid is an upper bound
@@ -393,7 +394,7 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_agg_part(const uint16_t* __restri
     const int2* TOP = reinterpret_cast<const int2*>(bins + (size_t)(Gp + 1) * L);
     if (it.nchunks == 1) {
         for (int g = threadIdx.x; g < Gp; g += AGG_BLOCK)
-            fold_into_state<AT, L>(bins + g, Gp + 1, TOP[g].x, S, C, G, g0 + g);
+            fold_into_state<AT, L>(bins + g, Gp + 1, TOP[g].x, S, C, Gstride, gbase + g0 + g);
     } else {
         for (int g = threadIdx.x; g < Gp; g += AGG_BLOCK) {
             ptop[(size_t)blockIdx.x * GP + g] = TOP[g].x;
@@ -465,7 +466,8 @@ template <class AT, int L>
 __global__ void __launch_bounds__(256) k_merge_part(const WorkItem* __restrict__ items, const int* __restrict__ nitems,
                                                     const int* __restrict__ wfirst, int F, int64_t G, int gp_shift,
                                                     const int* __restrict__ ptop, const long long* __restrict__ pK,
-                                                    AT* __restrict__ S, long long* __restrict__ C) {
+                                                    AT* __restrict__ S, long long* __restrict__ C, int64_t gbase,
+                                                    int64_t Gstride) {
     typedef Fmt<AT> F_;
     constexpr int c = F_::CARRY;
     const int GP = 1 << gp_shift;
@@ -476,8 +478,8 @@ __global__ void __launch_bounds__(256) k_merge_part(const WorkItem* __restrict__
     if (w0 >= *nitems) return;  // empty partition (trailing)
     const WorkItem it = items[w0];
     if (it.p != p || it.nchunks < 2) return;  // empty or already folded
-    const int64_t g = ((int64_t)p << gp_shift) + gl;
-    if (g >= G) return;
+    if (((int64_t)p << gp_shift) + gl >= G) return;
+    const int64_t g = gbase + ((int64_t)p << gp_shift) + gl;  // state index (row stride Gstride)
     const int ts = state_top(S[g]);
     int J = ts;
     // unrolled so that the loads of several work items are in flight at
@@ -488,8 +490,8 @@ __global__ void __launch_bounds__(256) k_merge_part(const WorkItem* __restrict__
 #pragma unroll
     for (int l = 0; l < L; ++l) {
         const int ls = l - (J - ts);
-        hi[l] = (ls >= 0) ? C[(size_t)ls * G + g] : 0;
-        lo[l] = (ls >= 0) ? state_lo(S[(size_t)ls * G + g]) : 0;
+        hi[l] = (ls >= 0) ? C[(size_t)ls * Gstride + g] : 0;
+        lo[l] = (ls >= 0) ? state_lo(S[(size_t)ls * Gstride + g]) : 0;
     }
 #pragma unroll 8
     for (int w = w0; w < w0 + it.nchunks; ++w) {
@@ -510,8 +512,8 @@ __global__ void __launch_bounds__(256) k_merge_part(const WorkItem* __restrict__
     for (int l = 0; l < L; ++l) {
         long long cc, oo;
         normalise<AT>(hi[l], lo[l], &cc, &oo);
-        S[(size_t)l * G + g] = make_S((AT*)0, F_::B + (J - l) * F_::W, oo);
-        C[(size_t)l * G + g] = cc;
+        S[(size_t)l * Gstride + g] = make_S((AT*)0, F_::B + (J - l) * F_::W, oo);
+        C[(size_t)l * Gstride + g] = cc;
     }
 }
 
@@ -717,17 +719,56 @@ bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
     return true;
 }
 
+// Two levels: super-partitions of 4096 one-level partitions each.
+bool make_plan_deep(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
+    Plan one;
+    memset(&one, 0, sizeof(one));
+    make_plan_part(1, 1, L, vsize, &one);  // the one-level partition size for L
+    memset(p, 0, sizeof(*p));
+    p->path = 3;
+    const int sshift = one.gp_shift + 12;
+    p->gp_shift = sshift;
+    const int64_t F = (G + ((int64_t)1 << sshift) - 1) >> sshift;
+    if (F > DEEP_MAX_F) return false;
+    p->F = (int)F;
+    p->sc_ru = 8;
+    p->lds_sc = (size_t)F * 16 + (size_t)8 * PART_BLOCK * (vsize + 6);
+    int64_t nw = (n + (int64_t)PART_BLOCK * 16 - 1) / ((int64_t)PART_BLOCK * 16);
+    nw = std::max<int64_t>(1, std::min<int64_t>(PART_WG, nw));
+    p->nw = (int)nw;
+    p->chunk_hs = std::max<int64_t>(1, (n + nw - 1) / nw);
+    size_t ws = 0;
+    auto take = [&](size_t bytes) { size_t o = ws; ws += align_up(bytes, 256); return o; };
+    p->o_counts = take((size_t)nw * F * 4);
+    p->o_rel = take((size_t)nw * F * 4);
+    p->o_size = take((size_t)F * 8);
+    p->o_base = take((size_t)F * 8);
+    p->o_lkey = take((size_t)n * 4);
+    p->o_lval = take((size_t)n * vsize);
+    Plan two;
+    memset(&two, 0, sizeof(two));
+    if (!make_plan_part(n, (int64_t)1 << sshift, L, vsize, &two)) return false;
+    p->ws_l2 = two.ws;  // the largest one-level workspace of a super-partition
+    p->o_l2 = take(two.ws);
+    p->ws = ws;
+    return true;
+}
+
 bool make_plan(int64_t n, int64_t G, int L, int jmax, size_t vsize, Plan* p) {
     if (agg_lds_bytes(G, L, 1) > LDS_BIN_BUDGET) {
         memset(p, 0, sizeof(*p));
-        return make_plan_part(n, G, L, vsize, p);
+        if (make_plan_part(n, G, L, vsize, p)) return true;
+        return make_plan_deep(n, G, L, vsize, p);
     }
     return make_plan_lds(n, G, L, jmax, AGG_TILE, p);
 }
 
+// gbase, Gstride: the call's groups are states' groups gbase .. gbase+G-1 of
+// Gstride (the second partitioning level runs one call per super-partition).
 template <class KT, class VT, class AT, int L>
 int run_groupby_part(const void* keys, const void* values, int64_t n, int64_t G, void* states, void* workspace,
-                     uint32_t* status, const Plan& p, hipStream_t st) {
+                     uint32_t* status, const Plan& p, hipStream_t st, int64_t gbase = 0, int64_t Gstride = -1) {
+    if (Gstride < 0) Gstride = G;
     unsigned char* ws = static_cast<unsigned char*>(workspace);
     const KT* k = static_cast<const KT*>(keys);
     const VT* v = static_cast<const VT*>(values);
@@ -743,8 +784,8 @@ int run_groupby_part(const void* keys, const void* values, int64_t n, int64_t G,
     int* ptop = reinterpret_cast<int*>(ws + p.o_ptop);
     long long* pK = reinterpret_cast<long long*>(ws + p.o_pK);
     AT* S = static_cast<AT*>(states);
-    long long* C =
-        reinterpret_cast<long long*>(static_cast<unsigned char*>(states) + align_up((size_t)G * L * sizeof(AT), 8));
+    long long* C = reinterpret_cast<long long*>(static_cast<unsigned char*>(states) +
+                                                align_up((size_t)Gstride * L * sizeof(AT), 8));
     const size_t lds_h = (size_t)p.F * 4;
     const void* scatter = p.sc_ru == 8 ? (const void*)k_part_scatter<KT, VT, AT, 8> : (const void*)k_part_scatter<KT, VT, AT, 4>;
     if (!allow_lds((const void*)k_part_hist<KT>, lds_h) || !allow_lds(scatter, p.lds_sc) ||
@@ -769,13 +810,77 @@ int run_groupby_part(const void* keys, const void* values, int64_t n, int64_t G,
     prof_after(st);
     prof_before(st);
     hipLaunchKernelGGL((k_agg_part<VT, AT, L>), dim3(p.maxw), dim3(AGG_BLOCK), p.lds_agg2, st, lkey, lval, items,
-                       nitems, G, p.gp_shift, ptop, pK, S, C, status);
+                       nitems, G, p.gp_shift, ptop, pK, S, C, gbase, Gstride, status);
     LAUNCH_CHECK();
     prof_after(st);
     const int GP = 1 << p.gp_shift;
     hipLaunchKernelGGL((k_merge_part<AT, L>), dim3((GP + 255) / 256, p.F), dim3(256), 0, st, items, nitems, wfirst,
-                       p.F, G, p.gp_shift, ptop, pK, S, C);
+                       p.F, G, p.gp_shift, ptop, pK, S, C, gbase, Gstride);
     LAUNCH_CHECK();
+    return REPRO_OK;
+}
+
+// Two partitioning levels (Alg. 4 at depth 2), for more groups than 4096
+// partitions hold: rows are first scattered on the key's high bits into
+// super-partitions of 2^sshift groups (local keys as uint32), then every
+// non-empty super-partition runs the one-level path on its rows, into its
+// range of the states.  The super-partition sizes are read back to the host
+// once (the call waits for its stream there).
+__global__ void k_part_bases(const long long* __restrict__ size, int F, long long* __restrict__ base) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    long long b = 0;
+    for (int p = 0; p < F; ++p) {
+        base[p] = b;
+        b += size[p];
+    }
+}
+
+template <class KT, class VT, class AT, int L>
+int run_groupby_deep(const void* keys, const void* values, int64_t n, int64_t G, void* states, void* workspace,
+                     uint32_t* status, const Plan& p, hipStream_t st) {
+    unsigned char* ws = static_cast<unsigned char*>(workspace);
+    const KT* k = static_cast<const KT*>(keys);
+    const VT* v = static_cast<const VT*>(values);
+    int* counts = reinterpret_cast<int*>(ws + p.o_counts);
+    int* rel = reinterpret_cast<int*>(ws + p.o_rel);
+    long long* size = reinterpret_cast<long long*>(ws + p.o_size);
+    long long* base = reinterpret_cast<long long*>(ws + p.o_base);
+    uint32_t* lkey = reinterpret_cast<uint32_t*>(ws + p.o_lkey);
+    VT* lval = reinterpret_cast<VT*>(ws + p.o_lval);
+    const size_t lds_h = (size_t)p.F * 4;
+    if (!allow_lds((const void*)k_part_hist<KT>, lds_h) ||
+        !allow_lds((const void*)k_part_scatter<KT, VT, AT, 8, true, uint32_t>, p.lds_sc))
+        return REPRO_EHIP;
+    hipLaunchKernelGGL(k_part_hist<KT>, dim3(p.nw), dim3(PART_BLOCK), lds_h, st, k, n, G, p.gp_shift, p.F, p.chunk_hs,
+                       counts);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_part_offsets, dim3(p.F), dim3(PART_WG), 0, st, counts, p.nw, p.F, rel, size);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_part_bases, dim3(1), dim3(64), 0, st, size, p.F, base);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_part_scatter<KT, VT, AT, 8, true, uint32_t>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k,
+                       v, n, G, p.gp_shift, p.F, p.chunk_hs, base, rel, lkey, lval, status);
+    LAUNCH_CHECK();
+    long long hsize[DEEP_MAX_F];
+    if (hipMemcpyAsync(hsize, size, (size_t)p.F * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return REPRO_EHIP;
+    unsigned char* ws2 = ws + p.o_l2;
+    long long b = 0;
+    for (int sp = 0; sp < p.F; ++sp) {
+        const int64_t ns = hsize[sp];
+        const int64_t g0 = (int64_t)sp << p.gp_shift;
+        const int64_t Gs = std::min<int64_t>((int64_t)1 << p.gp_shift, G - g0);
+        if (ns > 0) {
+            Plan p2;
+            memset(&p2, 0, sizeof(p2));
+            if (!make_plan_part(ns, Gs, L, sizeof(VT), &p2) || p2.ws > p.ws_l2) return REPRO_EHIP;
+            const int rc = run_groupby_part<uint32_t, VT, AT, L>(lkey + b, lval + b, ns, Gs, states, ws2, status, p2,
+                                                                  st, g0, G);
+            if (rc != REPRO_OK) return rc;
+        }
+        b += ns;
+    }
     return REPRO_OK;
 }
 
@@ -783,6 +888,7 @@ template <class KT, class VT, class AT, int L>
 int run_groupby(const void* keys, const void* values, int64_t n, int64_t G64, void* states, void* workspace,
                 uint32_t* status, const Plan& p, hipStream_t st) {
     if (p.path == 2) return run_groupby_part<KT, VT, AT, L>(keys, values, n, G64, states, workspace, status, p, st);
+    if (p.path == 3) return run_groupby_deep<KT, VT, AT, L>(keys, values, n, G64, states, workspace, status, p, st);
     const int G = (int)G64;
     unsigned char* ws = static_cast<unsigned char*>(workspace);
     int* ptop = reinterpret_cast<int*>(ws);

@@ -225,7 +225,7 @@ inline int merge_pb(int nwg, int G) {
 }
 
 struct Plan {
-    int path;       // 1: LDS bins over all groups, 2: partitioned
+    int path;       // 1: LDS bins over all groups, 2: partitioned, 3: two partitioning levels
     // path 2
     int gp_shift, F, nw;     // groups per partition 2^gp_shift, partitions, hist/scatter workgroups
     size_t lds_sc;           // scatter LDS
@@ -234,6 +234,7 @@ struct Plan {
     int maxw;                // work items, upper bound
     size_t o_counts, o_rel, o_size, o_base, o_wfirst, o_items, o_nitems, o_lkey, o_lval, o_ptop, o_pK;
     size_t lds_agg2;         // LDS of k_agg_part
+    size_t o_l2, ws_l2;      // path 3: the one-level workspace of a super-partition, and its size
     int nwg;        // aggregate workgroups
     int64_t chunk;  // rows per workgroup (multiple of the tile)
     int R;          // LDS bin replicas

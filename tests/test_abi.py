@@ -84,6 +84,14 @@ def test_noalloc_entry_rejects_without_gpu(lib):
     assert lib.repro_groupby_sum_noalloc(null, 0, null, 1, 0, 4, 1, 2, p, null, null) == _lib.REPRO_OK
 
 
+def test_every_group_count_has_a_plan(lib):
+    # one LDS workgroup, one partitioning level, two levels, up to 2^31 - 1 groups
+    for L in (1, 2, 3, 4):
+        for G in (16, 10 ** 5, (1 << 23) + 1, (1 << 24) + 1, 10 ** 9, (1 << 31) - 1):
+            assert lib.repro_workspace_bytes(10 ** 6, G, _lib.I64, _lib.F64, _lib.F64, L) > 0, (L, G)
+    assert lib.repro_workspace_bytes(10 ** 6, 1 << 31, _lib.I64, _lib.F64, _lib.F64, 2) == 0
+
+
 def test_plain_baseline_workspace_and_probe_checks(lib):
     # groups that fit LDS need no workspace; beyond, the partitioned baseline does
     assert lib.repro_plain_workspace_bytes(10 ** 6, 1024, _lib.I32, _lib.F64) == 0

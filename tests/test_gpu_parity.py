@@ -435,6 +435,25 @@ def test_mid_cardinality_lds_path_large_lds():
         check_case(keys, vals, G, L, True, "mid cardinality")
 
 
+@pytest.mark.parametrize("L,G", [(2, (1 << 24) + 1000), (4, (1 << 23) + 5), (1, (1 << 26) + 3)])
+def test_two_partitioning_levels(L, G):
+    """More groups than one partitioning level holds: a first scatter into
+    super-partitions, then the one-level path per super-partition; bad keys
+    and non-finite values on the way, and a resumed second call."""
+    rng = np.random.default_rng([L, G % 1000])
+    n = 2_000_000
+    keys = rng.integers(-3, G + 3, n).astype(np.int64)
+    keys[: n // 4] = rng.integers(G - 2000, G, n // 4)  # the last, small super-partition gets rows too
+    vals = np.ldexp(rng.standard_normal(n), rng.integers(-200, 200, n))
+    vals[rng.random(n) < 1e-4] = np.nan
+    check_case(keys, vals, G, L, True, f"two partitioning levels G={G} L={L}")
+    orc, _ = O.groupby_sum(keys, vals, G, L)
+    st = api.groupby_sum(dev(keys[:700_001]), dev(vals[:700_001]), G, L)
+    st = api.groupby_sum(dev(keys[700_001:]), dev(vals[700_001:]), G, L, states=st)
+    torch.cuda.synchronize()
+    assert_same_states(st, orc, G, L, True, "two levels, resumed")
+
+
 def test_partitioned_many_partitions_small_tiles():
     """Thousands of partitions (the scatter falls back to 4096-row tiles)."""
     rng = np.random.default_rng(55)
