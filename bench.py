@@ -456,7 +456,9 @@ def bench_serve(args):
 
     from paper_1802_09883_amd import api, workloads
 
-    Q, slots = 128, 8
+    Q = 128
+    slots = int(os.environ.get("REPRO_SERVE_SLOTS", "8"))
+    max_bypass = int(os.environ.get("REPRO_SERVE_BYPASS", "8"))
     rows, groups, gaps = workloads.served_queries(Q)
     n_all = int(rows.sum())
     log(f"generating {Q} queries, {n_all} rows")
@@ -477,7 +479,7 @@ def bench_serve(args):
     qwg = int(os.environ.get("REPRO_QUERY_WG", "0"))  # persistent workgroups per query (0: all)
 
     def run(arrivals):
-        srv = api.Server(arena, slots=slots, query_workgroups=qwg)
+        srv = api.Server(arena, slots=slots, query_workgroups=qwg, max_bypass=max_bypass)
         try:
             t0 = srv.clock()
             arr = t0 + arrivals
@@ -528,7 +530,8 @@ def bench_serve(args):
         "steps": 1, "warmup": 1, "ms_per_step": round(span_c * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": CONFIGS["serve"]["desc"].format(q=Q, n=n_all, slots=slots), "name": "serve",
-                   "queries": Q, "rows": n_all, "slots": slots, "parallelism": "single GPU"},
+                   "queries": Q, "rows": n_all, "slots": slots, "max_bypass": max_bypass,
+                   "query_workgroups": qwg, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4), "mean": round(float(np.mean(lat)) * 1e3, 4),
                        "offered_rate_qps": round(rate, 2), "open_loop_rows_per_s": n_all / span_o},
         "step_hbm_frac": round(ach / HBM_PEAK_GBS, 4),

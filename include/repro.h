@@ -353,6 +353,10 @@ typedef struct {
     int query_workgroups;  /* on the batch path, persistent workgroups per query
                               (0: as many as the GPU holds).  Fewer let queries
                               of other slots run beside a long one           */
+    int max_bypass;      /* a queued query whose memory does not fit yet may be
+                            passed by later queries that fit, at most this many
+                            times; then admission waits for it (0: strict
+                            arrival order)                                    */
 } repro_server_config;
 
 typedef struct repro_server repro_server;
@@ -371,7 +375,9 @@ int repro_server_create(void* arena, size_t arena_bytes, const repro_server_conf
 int repro_server_submit(repro_server* srv, const repro_query* q, int64_t* ticket);
 
 /* Makes progress without blocking: retires finished queries (freeing their
- * memory and slot), then admits queued queries in order while they fit.
+ * memory and slot), then admits queued queries in arrival order while slots
+ * are free and their memory fits (a query that does not fit may be passed by
+ * later ones up to max_bypass times).
  * Writes up to `cap` completed tickets and their completion times (seconds
  * on the host's monotonic clock); a finished query beyond `cap` stays in its
  * slot and is reported by a later call.  Always writes the counts of

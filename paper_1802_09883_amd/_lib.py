@@ -48,7 +48,7 @@ class Query(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     """repro_server_config of include/repro.h."""
     _fields_ = [("slots", ctypes.c_int), ("chunk_rows", ctypes.c_int64), ("no_batch_path", ctypes.c_int),
-                ("query_workgroups", ctypes.c_int)]
+                ("query_workgroups", ctypes.c_int), ("max_bypass", ctypes.c_int)]
 
 
 class BatchPlan(ctypes.Structure):

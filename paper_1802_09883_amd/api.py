@@ -460,10 +460,11 @@ class Server:
     queues a query, poll() retires finished queries and admits queued ones
     without blocking."""
 
-    def __init__(self, arena_bytes, slots=4, chunk_rows=0, batch_path=True, query_workgroups=0, device="cuda"):
+    def __init__(self, arena_bytes, slots=4, chunk_rows=0, batch_path=True, query_workgroups=0, max_bypass=0,
+                 device="cuda"):
         self.lib = _lib.load()
         self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=device)
-        self.cfg = _lib.ServerConfig(slots, chunk_rows, 0 if batch_path else 1, query_workgroups)
+        self.cfg = _lib.ServerConfig(slots, chunk_rows, 0 if batch_path else 1, query_workgroups, max_bypass)
         h = ctypes.c_void_p()
         _lib.check(self.lib.repro_server_create(_vp(self.arena), arena_bytes, ctypes.byref(self.cfg),
                                                 ctypes.byref(h)), "server_create")

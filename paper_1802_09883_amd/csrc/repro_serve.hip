@@ -183,6 +183,7 @@ bool layout_query(const repro_query* q, int64_t chunk_cfg, bool batch_path, Quer
 struct Pending {
     int64_t ticket;
     repro_query q;
+    int bypassed = 0;  // later queries admitted ahead of this one
 };
 
 struct Slot {
@@ -206,6 +207,7 @@ struct repro_server {
     int64_t chunk = SERVE_DEFAULT_CHUNK;
     bool batch_path = true;
     int query_wg = 0;
+    int max_bypass = 0;
     Arena alloc;
     std::vector<Slot> slots;
     std::deque<Pending> queue;
@@ -289,13 +291,16 @@ double repro_server_clock(void) { return now_s(); }
 int repro_server_create(void* arena, size_t arena_bytes, const repro_server_config* cfg, repro_server** srv) {
     if (!srv || !arena || (uintptr_t)arena % SERVE_ALIGN != 0 || arena_bytes < SERVE_ALIGN) return REPRO_EINVAL;
     const int nslots = cfg ? cfg->slots : 4;
-    if (nslots < 1 || nslots > 64 || (cfg && (cfg->chunk_rows < 0 || cfg->query_workgroups < 0))) return REPRO_EINVAL;
+    if (nslots < 1 || nslots > 64 ||
+        (cfg && (cfg->chunk_rows < 0 || cfg->query_workgroups < 0 || cfg->max_bypass < 0)))
+        return REPRO_EINVAL;
     repro_server* s = new repro_server();
     s->arena = static_cast<unsigned char*>(arena);
     s->arena_bytes = arena_bytes / SERVE_ALIGN * SERVE_ALIGN;
     s->chunk = (cfg && cfg->chunk_rows > 0) ? cfg->chunk_rows : SERVE_DEFAULT_CHUNK;
     s->batch_path = !(cfg && cfg->no_batch_path);
     s->query_wg = cfg ? cfg->query_workgroups : 0;
+    s->max_bypass = cfg ? cfg->max_bypass : 0;
     s->alloc.init(s->arena_bytes);
     s->slots.resize(nslots);
     for (Slot& sl : s->slots) {
@@ -346,7 +351,9 @@ int repro_server_poll(repro_server* s, int64_t* tickets, double* times, int cap,
         sl.busy = false;
         sl.ticket = -1;
     }
-    // admit, in order, while a slot and memory are free
+    // admit in arrival order while a slot is free: the first queued query
+    // whose memory fits; one that does not fit is passed by later ones at
+    // most max_bypass times, then admission waits for it (no starvation)
     while (rc == REPRO_OK && !s->queue.empty()) {
         Slot* free_slot = nullptr;
         for (Slot& sl : s->slots)
@@ -355,20 +362,28 @@ int repro_server_poll(repro_server* s, int64_t* tickets, double* times, int cap,
                 break;
             }
         if (!free_slot) break;
-        const Pending& p = s->queue.front();
+        auto pick = s->queue.end();
         QueryLayout ly;
-        if (!layout_query(&p.q, s->chunk, s->batch_path, &ly)) {  // validated at submission: cannot happen
-            rc = REPRO_EINVAL;
-            break;
-        }
         size_t off = 0;
-        if (!s->alloc.alloc(ly.total, &off)) break;  // wait for memory
+        for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
+            if (!layout_query(&it->q, s->chunk, s->batch_path, &ly)) {  // validated at submission: cannot happen
+                rc = REPRO_EINVAL;
+                break;
+            }
+            if (s->alloc.alloc(ly.total, &off)) {
+                pick = it;
+                break;
+            }
+            if (it->bypassed >= s->max_bypass) break;  // aged: wait for its memory
+        }
+        if (pick == s->queue.end()) break;
+        for (auto it = s->queue.begin(); it != pick; ++it) ++it->bypassed;
         free_slot->busy = true;
-        free_slot->ticket = p.ticket;
+        free_slot->ticket = pick->ticket;
         free_slot->off = off;
         free_slot->bytes = ly.total;
-        const repro_query q = p.q;
-        s->queue.pop_front();
+        const repro_query q = pick->q;
+        s->queue.erase(pick);
         if (enqueue_query(s, *free_slot, q, ly) != REPRO_OK) {
             // drop the query: let what was enqueued finish before its memory
             // and slot are reused, report its ticket and stop admitting

@@ -150,7 +150,7 @@ def test_query_bytes_without_gpu(lib):
     q.n, q.num_groups, q.L, q.naggs = 1_000_000, 1000, 2, 4
     for i, (a, b) in enumerate(((0, -1), (1, -1), (2, 3), (4, 5))):
         q.agg_a[i], q.agg_b[i], q.out[i] = a, b, 0x9000000 + 0x10000 * i
-    cfg = _lib.ServerConfig(4, 1 << 20)
+    cfg = _lib.ServerConfig(4, 1 << 20, 0, 0, 0)
     need = lib.repro_query_bytes(ctypes.byref(q), ctypes.byref(cfg))
     # four states, two product columns (8 B per row each), one chunk's workspace
     assert need >= 4 * lib.repro_state_bytes(1000, _lib.F64, 2) + 2 * 8 * 1_000_000
@@ -160,5 +160,8 @@ def test_query_bytes_without_gpu(lib):
     q.cols[5] = None  # a product aggregate without its column
     assert lib.repro_query_bytes(ctypes.byref(q), ctypes.byref(cfg)) == 0
     srv = ctypes.c_void_p()
+    bad = _lib.ServerConfig(4, 1 << 20, 0, 0, -1)  # negative bypass bound
+    assert lib.repro_server_create(ctypes.c_void_p(256), 1 << 20, ctypes.byref(bad), ctypes.byref(srv)) == \
+        _lib.REPRO_EINVAL
     assert lib.repro_server_create(ctypes.c_void_p(257), 1 << 20, ctypes.byref(cfg), ctypes.byref(srv)) == \
         _lib.REPRO_EINVAL  # misaligned arena, rejected before any GPU call

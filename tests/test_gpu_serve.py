@@ -199,3 +199,45 @@ def test_poll_reports_every_completion_within_cap():
     for s in specs:
         assert np.array_equal(s.out[0].cpu().numpy(), want)
 
+
+
+@pytest.mark.parametrize("max_bypass", [0, 1, 4])
+def test_admission_bypass_with_aging(max_bypass):
+    """A queued query whose memory does not fit yet is passed by later
+    queries that fit at most max_bypass times (0: strict arrival order);
+    every result still equals the oracle."""
+    G = 3000
+    sizes = [2_000_000, 4_000_000, 20_000, 20_000]  # A runs; B does not fit beside it; C and D do
+    pool = WL.decimal_columns(max(sizes), 6, salt=7)
+    pool_t = [torch.from_numpy(np.ascontiguousarray(c)).cuda() for c in pool]
+    host, specs = [], []
+    for q, n in enumerate(sizes):
+        keys = WL.served_keys(n, G, q, salt=7)
+        host.append(keys)
+        specs.append(api.QuerySpec(torch.from_numpy(keys).cuda(), [c[:n] for c in pool_t], G, WL.SERVED_AGGS, L=2))
+    probe = api.Server(1 << 32, slots=4, chunk_rows=300_000)
+    need = [probe.query_bytes(s) for s in specs]
+    probe.close()
+    # B alone fits the arena, and so do A, C and D together, but not A and B
+    arena = max(need[1], sum(need[i] // 256 * 256 + 512 for i in (0, 2, 3))) // 256 * 256 + 512
+    assert need[1] <= arena < need[0] + need[1]
+    srv = api.Server(arena, slots=4, chunk_rows=300_000, max_bypass=max_bypass)
+    try:
+        for s in specs:
+            srv.submit(s)
+        _, nq, nr = srv.poll()
+        # strict: A only; one bypass: A and C (B aged, D waits); more: A, C and D
+        want_running = {0: 1, 1: 2, 4: 3}[max_bypass]
+        assert (nr, nq) == (want_running, 4 - want_running), (nr, nq)
+        seen = 0
+        t0 = time.time()
+        while seen < 4:
+            done, nq, nr = srv.poll()
+            seen += len(done)
+            assert time.time() - t0 < 120, "server did not finish"
+        torch.cuda.synchronize()
+    finally:
+        srv.close()
+    for s, keys, n in zip(specs, host, sizes):
+        for o, r in zip(s.out, oracle_sums(pool, keys, 0, n, G)):
+            assert np.array_equal(o.cpu().numpy(), r)
