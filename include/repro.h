@@ -271,6 +271,9 @@ typedef struct {
     int64_t chunk_rows;   /* rows per item (rounded up to a multiple of 8192)  */
     int max_slice_groups; /* cap on the groups of one slice (bins per LDS)     */
     int order;            /* 0: largest items first, 1: job order              */
+    int merge;            /* merge schedule of jobs cut into several chunks:
+                             0: the last chunk to finish merges (in the
+                             persistent launch), 1: a merge launch after it   */
 } repro_batch_config;
 
 /* Plan handle filled by repro_batch_prepare (host memory, plain data). */
@@ -297,14 +300,14 @@ int repro_batch_prepare(const repro_batch_job* jobs, int njobs, repro_key_t kt, 
                         repro_batch_plan* plan, hipStream_t stream);
 
 /* Runs a prepared batch on `stream`: a reset kernel, then the persistent
- * kernel.  status as for repro_groupby_sum (may be NULL).  Jobs that
+ * kernel (and the merge kernel under merge schedule 1).  status as for repro_groupby_sum (may be NULL).  Jobs that
  * accumulate must see their states' previous contents, so two launches of
  * the same plan add the batch twice; jobs that overwrite give the same
  * states every launch. */
 int repro_batch_launch(const repro_batch_plan* plan, uint32_t* status, hipStream_t stream);
 
 /* Autotuner: times the candidate configurations (chunk rows, slice cap,
- * order) on this batch and writes the fastest to *best (and its time in ms
+ * order, merge schedule) on this batch and writes the fastest to *best (and its time in ms
  * to *best_ms, if not NULL).  It runs the batch many times: the jobs'
  * states and outputs hold unspecified values afterwards.  Candidates whose
  * workspace exceeds workspace_bytes are skipped.  Blocks until done. */

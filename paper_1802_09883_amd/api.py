@@ -357,7 +357,7 @@ def _batch_config(config):
     if config is None:
         return None
     return ctypes.byref(_lib.BatchConfig(int(config.get("chunk_rows", 0)), int(config.get("max_slice_groups", 0)),
-                                         int(config.get("order", 0))))
+                                         int(config.get("order", 0)), int(config.get("merge", 0))))
 
 
 class BatchRun:
@@ -415,7 +415,8 @@ def batch_tune(jobs, T=torch.float64, stream=None):
     arr = _batch_jobs(jobs)
     kt, vt = _KEY[jobs[0].keys.dtype], _SCALAR[jobs[0].values.dtype]
     need = max(lib.repro_batch_workspace_bytes(arr, len(jobs), kt, vt, _T(T),
-                                               _batch_config({"chunk_rows": c})) for c in (65536, 131072))
+                                               _batch_config({"chunk_rows": c, "merge": m}))
+               for c in (65536, 131072) for m in (0, 1))
     s = stream if stream is not None else torch.cuda.current_stream(dev)
     with torch.cuda.stream(s):
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
@@ -423,7 +424,8 @@ def batch_tune(jobs, T=torch.float64, stream=None):
     ms = ctypes.c_float(0)
     _lib.check(lib.repro_batch_tune(arr, len(jobs), kt, vt, _T(T), _vp(ws), need, ctypes.byref(best),
                                     ctypes.byref(ms), ctypes.c_void_p(s.cuda_stream)), "batch_tune")
-    return {"chunk_rows": best.chunk_rows, "max_slice_groups": best.max_slice_groups, "order": best.order}, ms.value
+    return {"chunk_rows": best.chunk_rows, "max_slice_groups": best.max_slice_groups, "order": best.order,
+            "merge": best.merge}, ms.value
 
 
 # ----------------------------------------------------------------- serving

@@ -68,18 +68,28 @@ struct BatchHead {
     int ncounters;
     long long off_jobs, off_items, off_counters, off_spill, off_partials;
     long long zero_words;  // 8-byte words from off_counters that k_batch_reset clears
+    int merge;             // 0: the last item of a (job, slice) merges; 1: a merge launch after the batch
+    int nunits;            // merge launch: work units (256 groups of one split job each)
+    long long off_units;
 };
+
+// A work unit of the merge launch: groups g0 .. g0+255 of a split job.
+struct MergeUnit {
+    int job, g0;
+};
+constexpr int MERGE_UNIT = 256;
 
 struct BatchLayout {
-    size_t jobs, items, counters, spill, partials, total;
+    size_t jobs, items, units, counters, spill, partials, total;
 };
 
-inline BatchLayout batch_layout(int njobs, int64_t nitems, int64_t ncounters, size_t spill_bytes,
+inline BatchLayout batch_layout(int njobs, int64_t nitems, int64_t nunits, int64_t ncounters, size_t spill_bytes,
                                 size_t partial_bytes) {
     BatchLayout b;
     b.jobs = 256;
     b.items = b.jobs + align_up((size_t)njobs * sizeof(BatchJob), 256);
-    b.counters = b.items + align_up((size_t)nitems * sizeof(BatchItem), 256);
+    b.units = b.items + align_up((size_t)nitems * sizeof(BatchItem), 256);
+    b.counters = b.units + align_up((size_t)nunits * sizeof(MergeUnit), 256);
     b.spill = b.counters + align_up((size_t)ncounters * 4, 256);
     b.partials = b.spill + align_up(spill_bytes, 256);
     b.total = b.partials + align_up(partial_bytes, 256);
@@ -107,7 +117,8 @@ __device__ __forceinline__ int state_top_of(const AT* S, int g, bool use, int L)
 // slice folds the slice.  Returns the lane's status bits.
 template <class KT, class VT, class AT, int L, int VEC, bool EPOCH>
 __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned char* partials, int* counters,
-                             unsigned long long* spill_area, unsigned char* smem, AggShared& sh, int* s_last) {
+                             unsigned long long* spill_area, unsigned char* smem, AggShared& sh, int* s_last,
+                             int merge) {
     constexpr int NJ = Fmt<AT>::JMAX + 1;
     const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)bi.chunk * jb.chunk;
@@ -164,6 +175,10 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
             for (int l = 0; l < L; ++l) publish(&pK[(size_t)l * jb.gs + g], x[l]);
         }
     }
+    if (merge) {  // the merge launch after the batch folds the partials
+        __syncthreads();  // LDS is reused by the next item
+        return err;
+    }
     published();  // this thread's partial words (and spill atomics) complete before the count
     __syncthreads();
     if (tid == 0) *s_last = (atomicAdd(&counters[jb.done_off + bi.slice], 1) == jb.nchunks - 1);
@@ -198,14 +213,64 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
 template <class KT, class VT, class AT, int L>
 __device__ __forceinline__ uint32_t run_item_vec(const BatchJob& jb, const BatchItem& bi, unsigned char* partials,
                                                  int* counters, unsigned long long* spill, unsigned char* smem,
-                                                 AggShared& sh, int* s_last) {
+                                                 AggShared& sh, int* s_last, int merge) {
     constexpr int VEC = 16 / sizeof(VT);
     if (jb.spill_off >= 0) {
-        if (jb.vec) return run_item<KT, VT, AT, L, VEC, true>(jb, bi, partials, counters, spill, smem, sh, s_last);
-        return run_item<KT, VT, AT, L, 1, true>(jb, bi, partials, counters, spill, smem, sh, s_last);
+        if (jb.vec)
+            return run_item<KT, VT, AT, L, VEC, true>(jb, bi, partials, counters, spill, smem, sh, s_last, merge);
+        return run_item<KT, VT, AT, L, 1, true>(jb, bi, partials, counters, spill, smem, sh, s_last, merge);
     }
-    if (jb.vec) return run_item<KT, VT, AT, L, VEC, false>(jb, bi, partials, counters, spill, smem, sh, s_last);
-    return run_item<KT, VT, AT, L, 1, false>(jb, bi, partials, counters, spill, smem, sh, s_last);
+    if (jb.vec) return run_item<KT, VT, AT, L, VEC, false>(jb, bi, partials, counters, spill, smem, sh, s_last, merge);
+    return run_item<KT, VT, AT, L, 1, false>(jb, bi, partials, counters, spill, smem, sh, s_last, merge);
+}
+
+// The merge launch (merge schedule 1): one 256-thread block per unit, one
+// thread per group of a split job: the group's chunk partials, the caller's
+// state (or the empty one) and the spill words fold into canonical states
+// and the finalised sum, exactly as the last item does under schedule 0.
+template <class AT, int L>
+__device__ __forceinline__ void merge_group(const BatchJob& jb, int g, const unsigned char* partials,
+                                            const unsigned long long* spill_area) {
+    constexpr int NJ = Fmt<AT>::JMAX + 1;
+    const int slice = g / jb.gs, gl = g - slice * jb.gs;
+    const size_t pbytes = partial_bytes(jb.gs, L);
+    const unsigned char* part0 = partials + jb.part_off + (size_t)slice * jb.nchunks * pbytes;
+    AT* S = S_ptr<AT>(jb.states);
+    long long* C = C_ptr<AT>(jb.states, jb.G, L);
+    long long hi[L], lo[L];
+    int J = state_top_of(S, g, jb.accumulate, L);
+#pragma unroll 4
+    for (int c = 0; c < jb.nchunks; ++c) J = max(J, reinterpret_cast<const int*>(part0 + (size_t)c * pbytes)[gl]);
+    start_from_state<AT, L>(S, C, jb.G, g, jb.accumulate, J, hi, lo);
+#pragma unroll 4
+    for (int c = 0; c < jb.nchunks; ++c) {
+        const unsigned char* pp = part0 + (size_t)c * pbytes;
+        const long long* pK = reinterpret_cast<const long long*>(pp + align_up((size_t)jb.gs * 4, 8));
+        long long x[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) x[l] = pK[(size_t)l * jb.gs + gl];
+        add_levels<AT, L>(x, reinterpret_cast<const int*>(pp)[gl], J, hi, lo);
+    }
+    if (jb.spill_off >= 0) add_spill<AT, L>(spill_area + jb.spill_off / 8 + (size_t)gl * NJ * 2, J, hi, lo);
+    write_group<AT, L>(hi, lo, J, S, C, jb.G, g, static_cast<AT*>(jb.out));
+}
+
+template <class AT>
+__global__ void __launch_bounds__(MERGE_UNIT) k_batch_merge(const unsigned char* __restrict__ ws) {
+    const BatchHead* hd = reinterpret_cast<const BatchHead*>(ws);
+    if ((int)blockIdx.x >= hd->nunits) return;
+    const MergeUnit u = reinterpret_cast<const MergeUnit*>(ws + hd->off_units)[blockIdx.x];
+    const BatchJob jb = reinterpret_cast<const BatchJob*>(ws + hd->off_jobs)[u.job];
+    const int g = u.g0 + (int)threadIdx.x;
+    if (g >= jb.G) return;
+    const unsigned char* partials = ws + hd->off_partials;
+    const unsigned long long* spill = reinterpret_cast<const unsigned long long*>(ws + hd->off_spill);
+    switch (jb.L) {
+        case 1: merge_group<AT, 1>(jb, g, partials, spill); break;
+        case 2: merge_group<AT, 2>(jb, g, partials, spill); break;
+        case 3: merge_group<AT, 3>(jb, g, partials, spill); break;
+        default: merge_group<AT, 4>(jb, g, partials, spill); break;
+    }
 }
 
 // Zeroes the queue position and the completion counters (a kernel, so that
@@ -233,6 +298,7 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch(unsigned char* __restrict
     unsigned long long* spill = reinterpret_cast<unsigned long long*>(ws + hd->off_spill);
     unsigned char* partials = ws + hd->off_partials;
     const int nitems = hd->nitems;
+    const int merge = hd->merge;
     uint32_t err = 0;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(&hd->next, 1);
@@ -243,10 +309,10 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch(unsigned char* __restrict
         const BatchItem bi = items[it];
         const BatchJob jb = jobs[bi.job];
         switch (jb.L) {
-            case 1: err |= run_item_vec<KT, VT, AT, 1>(jb, bi, partials, counters, spill, smem, sh, &s_last); break;
-            case 2: err |= run_item_vec<KT, VT, AT, 2>(jb, bi, partials, counters, spill, smem, sh, &s_last); break;
-            case 3: err |= run_item_vec<KT, VT, AT, 3>(jb, bi, partials, counters, spill, smem, sh, &s_last); break;
-            default: err |= run_item_vec<KT, VT, AT, 4>(jb, bi, partials, counters, spill, smem, sh, &s_last); break;
+            case 1: err |= run_item_vec<KT, VT, AT, 1>(jb, bi, partials, counters, spill, smem, sh, &s_last, merge); break;
+            case 2: err |= run_item_vec<KT, VT, AT, 2>(jb, bi, partials, counters, spill, smem, sh, &s_last, merge); break;
+            case 3: err |= run_item_vec<KT, VT, AT, 3>(jb, bi, partials, counters, spill, smem, sh, &s_last, merge); break;
+            default: err |= run_item_vec<KT, VT, AT, 4>(jb, bi, partials, counters, spill, smem, sh, &s_last, merge); break;
         }
     }
     report(status, err);
@@ -259,6 +325,8 @@ inline size_t scalar_bytes(repro_scalar_t t) { return t == REPRO_F64 ? 8 : 4; }
 struct HostPlan {
     std::vector<BatchJob> jobs;
     std::vector<BatchItem> items;
+    std::vector<MergeUnit> units;  // merge schedule 1
+    int merge = 0;
     int64_t ncounters = 0;
     size_t spill_bytes = 0;
     size_t partial_bytes = 0;
@@ -289,6 +357,10 @@ bool make_batch_plan(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
     const int cap_cfg = cfg ? cfg->max_slice_groups : 0;
     const int order = cfg ? cfg->order : 0;
     if (order != 0 && order != 1) return false;
+    const int merge = cfg ? cfg->merge : 0;
+    if (merge != 0 && merge != 1) return false;
+    hp->merge = merge;
+    hp->units.clear();
     const size_t ksz = kt == REPRO_I64 ? 8 : 4, vsz = scalar_bytes(vt);
     hp->jobs.resize(njobs);
     hp->items.clear();
@@ -337,6 +409,8 @@ bool make_batch_plan(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
             hp->spill_bytes += (size_t)b.gs * NJ * 16;
         }
         if (b.nchunks > 1) {
+            if (merge)
+                for (int g0 = 0; g0 < b.G; g0 += MERGE_UNIT) hp->units.push_back(MergeUnit{j, g0});
             b.done_off = (int)hp->ncounters;
             hp->ncounters += b.nslices;
             b.part_off = (long long)hp->partial_bytes;
@@ -348,7 +422,9 @@ bool make_batch_plan(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
                 cost.push_back(std::min<int64_t>(chunk, u.n - (int64_t)c * chunk));
             }
     }
-    if (hp->items.size() > (size_t)INT32_MAX / 2 || hp->ncounters > INT32_MAX / 2) return false;
+    if (hp->items.size() > (size_t)INT32_MAX / 2 || hp->ncounters > INT32_MAX / 2 ||
+        hp->units.size() > (size_t)INT32_MAX / 2)
+        return false;
     if (order == 0) {
         // largest first; the slices of one chunk stay together (they read the same rows)
         std::vector<int> idx(hp->items.size());
@@ -358,7 +434,8 @@ bool make_batch_plan(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
         for (size_t i = 0; i < idx.size(); ++i) sorted[i] = hp->items[idx[i]];
         hp->items.swap(sorted);
     }
-    hp->lay = batch_layout(njobs, (int64_t)hp->items.size(), hp->ncounters, hp->spill_bytes, hp->partial_bytes);
+    hp->lay = batch_layout(njobs, (int64_t)hp->items.size(), (int64_t)hp->units.size(), hp->ncounters,
+                           hp->spill_bytes, hp->partial_bytes);
     return true;
 }
 
@@ -385,6 +462,14 @@ int launch_plan(const repro_batch_plan* p, uint32_t* status, hipStream_t st) {
     void* args[] = {&ws, &status};
     if (hipLaunchKernel(fn, dim3(p->grid), dim3(BATCH_BLOCK), args, (size_t)p->lds_bytes, st) != hipSuccess)
         return REPRO_EHIP;
+    const int nunits = p->reserved[0];  // merge schedule 1: the merge launch
+    if (nunits > 0) {
+        if (p->T == REPRO_F64)
+            hipLaunchKernelGGL(k_batch_merge<double>, dim3(nunits), dim3(MERGE_UNIT), 0, st, ws);
+        else
+            hipLaunchKernelGGL(k_batch_merge<float>, dim3(nunits), dim3(MERGE_UNIT), 0, st, ws);
+        if (hipGetLastError() != hipSuccess) return REPRO_EHIP;
+    }
     return REPRO_OK;
 }
 
@@ -425,9 +510,13 @@ int plan_into(const repro_batch_job* jobs, int njobs, repro_key_t kt, repro_scal
     hd.off_spill = (long long)hp.lay.spill;
     hd.off_partials = (long long)hp.lay.partials;
     hd.zero_words = (long long)((hp.lay.partials - hp.lay.counters) / 8);
+    hd.merge = hp.merge;
+    hd.nunits = (int)hp.units.size();
+    hd.off_units = (long long)hp.lay.units;
     memcpy(img, &hd, sizeof(hd));
     if (njobs) memcpy(img + hp.lay.jobs, hp.jobs.data(), hp.jobs.size() * sizeof(BatchJob));
     if (!hp.items.empty()) memcpy(img + hp.lay.items, hp.items.data(), hp.items.size() * sizeof(BatchItem));
+    if (!hp.units.empty()) memcpy(img + hp.lay.units, hp.units.data(), hp.units.size() * sizeof(MergeUnit));
     // dynamic LDS beyond 64 KiB must be allowed per kernel; done here, on the
     // host and outside any graph capture of the launches
     if (hp.lds > 64 * 1024 && hipFuncSetAttribute(pick_kernel(kt, vt, T), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -441,6 +530,7 @@ int plan_into(const repro_batch_job* jobs, int njobs, repro_key_t kt, repro_scal
     plan->kt = kt;
     plan->vt = vt;
     plan->T = T;
+    plan->reserved[0] = (int)hp.units.size();  // units of the merge launch (merge schedule 1)
     return REPRO_OK;
 }
 
@@ -489,6 +579,7 @@ int repro_batch_tune(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
     const int64_t chunks[] = {65536, 131072, 262144, 524288};
     const int caps[] = {0, 1024};
     const int orders[] = {0, 1};
+    const int merges[] = {0, 1};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return REPRO_EHIP;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -499,8 +590,9 @@ int repro_batch_tune(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
     int rc = REPRO_OK;
     for (int64_t ch : chunks)
         for (int cap : caps)
-            for (int ord : orders) {
-                repro_batch_config c{ch, cap, ord};
+            for (int ord : orders)
+                for (int mg : merges) {
+                repro_batch_config c{ch, cap, ord, mg};
                 if (repro_batch_workspace_bytes(jobs, njobs, kt, vt, T, &c) > workspace_bytes) continue;
                 repro_batch_plan p;
                 rc = repro_batch_prepare(jobs, njobs, kt, vt, T, &c, workspace, workspace_bytes, &p, stream);

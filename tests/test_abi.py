@@ -124,7 +124,7 @@ def test_batch_workspace_and_validation_without_gpu(lib):
     need = lib.repro_batch_workspace_bytes(jobs, len(ok), _lib.I32, _lib.F64, _lib.F64, None)
     assert need > 0 and need % 256 == 0
     # the partial sums of split jobs grow with the number of chunks
-    small = _lib.BatchConfig(1 << 20, 0, 0)
+    small = _lib.BatchConfig(1 << 20, 0, 0, 0)
     assert lib.repro_batch_workspace_bytes(jobs, len(ok), _lib.I32, _lib.F64, _lib.F64, ctypes.byref(small)) < need
     for bad in ([(10, 0, 2)], [(10, 4, 0)], [(10, 4, 5)], [(-1, 4, 2)]):
         assert lib.repro_batch_workspace_bytes(_jobs(bad), 1, _lib.I32, _lib.F64, _lib.F64, None) == 0

@@ -88,19 +88,21 @@ def check_jobs(jobs, specs, priors, status, what):
     assert status == want_status, f"{what}: status {status} vs oracle {want_status}"
 
 
-def test_batch_matches_oracle_per_job():
+@pytest.mark.parametrize("config", [None, {"merge": 1, "chunk_rows": 65536}])
+def test_batch_matches_oracle_per_job(config):
     specs = mixed_jobs(1, 40)
-    say(f"case batch of {len(specs)} mixed jobs, {sum(len(s[0]) for s in specs)} rows")
+    say(f"case batch of {len(specs)} mixed jobs, {sum(len(s[0]) for s in specs)} rows, config {config}")
     jobs, priors = make_batch(specs, accumulate=lambda i: i % 3 == 1)
     status = torch.zeros(1, dtype=torch.int32, device="cuda")
-    api.batch_groupby_sum(jobs, status=status)
+    api.batch_groupby_sum(jobs, config=config, status=status)
     torch.cuda.synchronize()
     check_jobs(jobs, specs, priors, int(status.item()), "mixed batch")
 
 
 @pytest.mark.parametrize("config", [
     {"chunk_rows": 8192}, {"chunk_rows": 1 << 20}, {"max_slice_groups": 300}, {"order": 1},
-    {"chunk_rows": 16384, "max_slice_groups": 1000, "order": 1}])
+    {"chunk_rows": 16384, "max_slice_groups": 1000, "order": 1}, {"merge": 1}, {"chunk_rows": 8192, "merge": 1},
+    {"chunk_rows": 16384, "max_slice_groups": 300, "order": 1, "merge": 1}])
 def test_batch_configuration_does_not_change_bits(config):
     specs = mixed_jobs(2, 24, max_rows=200_000, errors=False)
     say(f"case batch config {config}")
