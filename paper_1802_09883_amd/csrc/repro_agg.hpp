@@ -229,6 +229,14 @@ __device__ __forceinline__ int jreq_raw(int f) {
     constexpr int add = (F::m - F::W + 2 - F::B + F::W - 2) * mul;
     return (int)((uint32_t)__mul24(f, mul) + (uint32_t)add) >> 16;
 }
+// Magnitude below which a value needs no top above J: |b| < 2^(W-1) *
+// ulp(S) at top J (the level-shift threshold of Alg. 2), so |b| < thr
+// exactly when jreq(b) <= J.  A power of two, exact in AT.
+template <class AT>
+__device__ __forceinline__ AT top_threshold(int J) {
+    typedef Fmt<AT> F;
+    return ldexp((AT)1, F::B + J * F::W - F::m + F::W - 1);
+}
 __device__ __forceinline__ int frexp_raw(double v) { return __builtin_amdgcn_frexp_exp(v); }
 __device__ __forceinline__ int frexp_raw(float v) { return __builtin_amdgcn_frexp_expf(v); }
 
@@ -337,6 +345,19 @@ struct SrcCol {
     template <class AT>
     __device__ __forceinline__ uint32_t errors(const Buf& b, uint32_t inr, int64_t G) const {
         return error_bits<KT, VT, AT>(b.k, b.v, inr, G);
+    }
+    // Full tile, one shared top (threshold thr, see top_threshold): a row
+    // whose key is a group and whose value is finite with |v| < thr goes to
+    // its group; any other row sets `slow` (it needs the general path).
+    template <class AT>
+    __device__ __forceinline__ void classify_fast(const Buf& b, int G, AT thr, int* gi, bool& slow) const {
+        const VT t = (VT)thr;  // exact, or 0 / inf beyond VT's range (then every row, resp. none, is slow)
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const bool ok = (uint64_t)(int64_t)b.k[i] < (uint64_t)G && finite_val(b.v[i]) && fabs(b.v[i]) < t;
+            gi[i] = ok ? (int)b.k[i] : G;
+            slow = slow || !ok;
+        }
     }
     template <class AT>
     __device__ __forceinline__ AT value(const Buf& b, int i) const {
@@ -452,6 +473,24 @@ struct SrcCols {
         }
     }
     template <class AT_>
+    __device__ __forceinline__ void classify_fast(const Buf& b, int G, AT_ thr, int* gi, bool& slow) const {
+        const float tf = (float)thr;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const bool kok = (uint64_t)(int64_t)b.k[r] < (uint64_t)Gc;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                bool ok;
+                if (stored_f32(c))
+                    ok = kok && finite_val(b.f[c][r]) && fabsf(b.f[c][r]) < tf;
+                else
+                    ok = kok && finite_val(b.d[c][r]) && fabs(b.d[c][r]) < (double)thr;
+                gi[c * RPT + r] = ok ? c * Gc + (int)b.k[r] : G;
+                slow = slow || !ok;
+            }
+        }
+    }
+    template <class AT_>
     __device__ __forceinline__ uint32_t errors(const Buf& b, uint32_t inr, int64_t) const {
         uint32_t e = 0;
 #pragma unroll
@@ -469,7 +508,8 @@ struct SrcCols {
     }
 };
 
-constexpr int EPOCH_TILES = 16;  // tiles between synchronisations in epoch mode
+constexpr int EPOCH_TILES = 16;       // tiles between synchronisations in epoch mode, at first
+constexpr int EPOCH_TILES_MAX = 256;  // after quiet epochs (no row spilled) the epoch doubles up to this
 constexpr int QUIET_TILES = 1;   // quiet per-tile synchronisations before epoch mode
 
 // The aggregation of rows [c0, c1) into LDS by one workgroup (the hot loop
@@ -520,8 +560,10 @@ __device__ __forceinline__ uint32_t aggregate_src(const Src& src, int64_t c0, in
     bool uni = true;   // all groups aligned to top Ju
     int Ju = L - 1;
     uint32_t hu = h_init;
+    AT thr = top_threshold<AT>(Ju);  // values below it need no top above Ju
     int sync = 0;      // synchronisations so far (selects the flag slot)
     int epoch_left = 0;  // tiles left in the current epoch (0: per-tile mode)
+    int epoch_len = EPOCH_TILES;  // tiles of the current epoch
     int quiet = 0;     // consecutive per-tile synchronisations without a raise
     bool ahead = false;  // this tile's tops were raised at the previous synchronisation
     if (EPOCH && seed) {
@@ -536,7 +578,8 @@ __device__ __forceinline__ uint32_t aggregate_src(const Src& src, int64_t c0, in
         uni = (sh.cnt == G);
         Ju = nm;
         hu = extractor_hi_of((AT*)0, Ju);
-        epoch_left = EPOCH_TILES;
+        thr = top_threshold<AT>(Ju);
+        epoch_left = epoch_len;
     }
 
     // Per-tile mode: when many lanes of a wave deposit into one group (skewed
@@ -616,6 +659,7 @@ __device__ __forceinline__ uint32_t aggregate_src(const Src& src, int64_t c0, in
         uni = (sh.cnt == G);
         Ju = nm;
         hu = extractor_hi_of((AT*)0, Ju);
+        thr = top_threshold<AT>(Ju);
         return true;
     };
 
@@ -640,8 +684,24 @@ __device__ __forceinline__ uint32_t aggregate_src(const Src& src, int64_t c0, in
         const Buf& bc = buf[0];
         const uint32_t inr_c = inr[0];
 
+        int gi[NR];
+        uint32_t hi_[NR];
+        // Epoch mode with one top for every group, full tile: when every row
+        // of the wave has a valid key and a finite value below the top's
+        // threshold, its group is all it needs (no error bits, no raise);
+        // otherwise the wave takes the general path below.  Waves decide
+        // apart: neither path synchronises the workgroup in epoch mode.
+        bool fast = false;
+        if constexpr (EPOCH && !SLICE) {
+            if (uni && epoch_left > 0 && base + TILE <= c1) {
+                bool slow = false;
+                src.template classify_fast<AT>(bc, G, thr, gi, slow);
+                fast = __ballot(slow) == 0;
+            }
+        }
+        if (!fast) {
         // classify: group (trash slot G for skipped rows) and required top
-        int gi[NR], ji[NR];
+        int ji[NR];
         bool clean = true;  // no row of this lane is an error row
         if (base + TILE <= c1)
             src.template classify<true, SLICE, AT>(bc, inr_c, G, gi, ji, clean, glo, Gfull);
@@ -652,7 +712,6 @@ __device__ __forceinline__ uint32_t aggregate_src(const Src& src, int64_t c0, in
 
         // tops of the rows' groups
         int ai[NR];
-        uint32_t hi_[NR];
         if (uni) {
 #pragma unroll
             for (int i = 0; i < NR; ++i) {
@@ -703,7 +762,7 @@ __device__ __forceinline__ uint32_t aggregate_src(const Src& src, int64_t c0, in
             flush_hot();
             const bool moved = synchronise(sp);
             quiet = moved ? 0 : quiet + 1;
-            if (EPOCH && quiet >= QUIET_TILES) epoch_left = EPOCH_TILES;
+            if (EPOCH && quiet >= QUIET_TILES) epoch_left = epoch_len = EPOCH_TILES;
             if (moved) {
                 if (uni) {
 #pragma unroll
@@ -728,6 +787,7 @@ __device__ __forceinline__ uint32_t aggregate_src(const Src& src, int64_t c0, in
             sh.flag[sync % 3] = 1;
             atomicAdd(&sh.spills[sync % 3], ns);
         }
+        }  // general path
         if (!EPOCH) {
             const int g0 = __builtin_amdgcn_readfirstlane(gi[0]);
             if (g0 != hot && g0 != G && __popcll(__ballot(gi[0] == g0)) >= HOT_MIN) {
@@ -785,7 +845,9 @@ __device__ __forceinline__ uint32_t aggregate_src(const Src& src, int64_t c0, in
             int sp;
             synchronise(sp);
             // many spills: the tops are still moving, go back to per-tile mode
-            epoch_left = (sp > TILE / 16) ? 0 : EPOCH_TILES;
+            // no spill: the tops have settled, synchronise half as often
+            epoch_len = sp == 0 ? min(2 * epoch_len, EPOCH_TILES_MAX) : EPOCH_TILES;
+            epoch_left = (sp > TILE / 16) ? 0 : epoch_len;
             quiet = 0;
         }
 #pragma unroll
