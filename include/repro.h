@@ -239,13 +239,15 @@ int repro_mul(const void* a, repro_scalar_t at, const void* b, repro_scalar_t bt
  * those of repro_groupby_sum on the same rows, whatever the batch, the
  * configuration or the schedule.  All jobs of a batch share kt, vt and T.
  *
- * Work is cut into items (job, row chunk, group slice): a job whose groups
- * do not fit one workgroup's LDS is cut into group slices, every item of a
- * slice reads the chunk and keeps only its slice's groups (the other items
- * of the chunk read it at about the same time, mostly from cache).  Items
- * are taken from a queue in order of decreasing size; the last item of a
- * (job, slice) to finish folds that slice's partial sums into the states
- * (and finalises them into `out`, when given).
+ * Work is cut into items (job, row chunk, group slice).  A job whose groups
+ * do not fit one workgroup's LDS is cut into group slices.  By default
+ * (split 0) one item per chunk sorts the chunk's rows by slice into a copy
+ * in the workspace and then aggregates each slice from its own rows (the
+ * chunk-local partitioning of Alg. 4); with split 1, or beyond 64 slices,
+ * every item of a slice reads the whole chunk and keeps only its slice's
+ * groups.  Items are taken from a queue in order of decreasing size; the
+ * last item of a (job, slice) to finish folds that slice's partial sums
+ * into the states (and finalises them into `out`, when given).
  *
  * Use: repro_batch_workspace_bytes -> repro_batch_prepare (host planning,
  * uploads the plan into the workspace and waits for that copy) ->
@@ -266,7 +268,7 @@ typedef struct {
 
 /* Tuning knobs.  None of them changes a result bit.  Zero fields take the
  * defaults (chunk_rows 131072, max_slice_groups as large as LDS allows,
- * order 0). */
+ * order 0, merge 0, split 0). */
 typedef struct {
     int64_t chunk_rows;   /* rows per item (rounded up to a multiple of 8192)  */
     int max_slice_groups; /* cap on the groups of one slice (bins per LDS)     */
@@ -274,6 +276,10 @@ typedef struct {
     int merge;            /* merge schedule of jobs cut into several chunks:
                              0: the last chunk to finish merges (in the
                              persistent launch), 1: a merge launch after it   */
+    int split;            /* jobs cut into group slices: 0: each chunk's rows
+                             are sorted by slice once (workspace holds the
+                             sorted copy, 2 + sizeof(vt) bytes per row), 1:
+                             every slice reads the whole chunk              */
 } repro_batch_config;
 
 /* Plan handle filled by repro_batch_prepare (host memory, plain data). */
@@ -307,7 +313,7 @@ int repro_batch_prepare(const repro_batch_job* jobs, int njobs, repro_key_t kt, 
 int repro_batch_launch(const repro_batch_plan* plan, uint32_t* status, hipStream_t stream);
 
 /* Autotuner: times the candidate configurations (chunk rows, slice cap,
- * order, merge schedule) on this batch and writes the fastest to *best (and its time in ms
+ * order, merge schedule, split) on this batch and writes the fastest to *best (and its time in ms
  * to *best_ms, if not NULL).  It runs the batch many times: the jobs'
  * states and outputs hold unspecified values afterwards.  Candidates whose
  * workspace exceeds workspace_bytes are skipped.  Blocks until done. */

@@ -31,7 +31,7 @@ class BatchJob(ctypes.Structure):
 class BatchConfig(ctypes.Structure):
     """repro_batch_config of include/repro.h."""
     _fields_ = [("chunk_rows", ctypes.c_int64), ("max_slice_groups", ctypes.c_int), ("order", ctypes.c_int),
-                ("merge", ctypes.c_int)]
+                ("merge", ctypes.c_int), ("split", ctypes.c_int)]
 
 
 MAX_COLS, MAX_AGGS = 8, 4

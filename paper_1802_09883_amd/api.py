@@ -357,7 +357,8 @@ def _batch_config(config):
     if config is None:
         return None
     return ctypes.byref(_lib.BatchConfig(int(config.get("chunk_rows", 0)), int(config.get("max_slice_groups", 0)),
-                                         int(config.get("order", 0)), int(config.get("merge", 0))))
+                                         int(config.get("order", 0)), int(config.get("merge", 0)),
+                                         int(config.get("split", 0))))
 
 
 class BatchRun:
@@ -414,9 +415,10 @@ def batch_tune(jobs, T=torch.float64, stream=None):
     dev = jobs[0].keys.device
     arr = _batch_jobs(jobs)
     kt, vt = _KEY[jobs[0].keys.dtype], _SCALAR[jobs[0].values.dtype]
-    need = max(lib.repro_batch_workspace_bytes(arr, len(jobs), kt, vt, _T(T),
-                                               _batch_config({"chunk_rows": c, "merge": m}))
-               for c in (65536, 131072) for m in (0, 1))
+    # the largest workspace over the candidates the tuner times
+    need = max(lib.repro_batch_workspace_bytes(arr, len(jobs), kt, vt, _T(T), _batch_config(
+        {"chunk_rows": c, "max_slice_groups": cap, "merge": m, "split": sp}))
+               for c in (65536, 131072, 262144, 524288) for cap in (0, 1024) for m in (0, 1) for sp in (0, 1))
     s = stream if stream is not None else torch.cuda.current_stream(dev)
     with torch.cuda.stream(s):
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
@@ -425,7 +427,7 @@ def batch_tune(jobs, T=torch.float64, stream=None):
     _lib.check(lib.repro_batch_tune(arr, len(jobs), kt, vt, _T(T), _vp(ws), need, ctypes.byref(best),
                                     ctypes.byref(ms), ctypes.c_void_p(s.cuda_stream)), "batch_tune")
     return {"chunk_rows": best.chunk_rows, "max_slice_groups": best.max_slice_groups, "order": best.order,
-            "merge": best.merge}, ms.value
+            "merge": best.merge, "split": best.split}, ms.value
 
 
 # ----------------------------------------------------------------- serving

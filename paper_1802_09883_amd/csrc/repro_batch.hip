@@ -9,13 +9,18 @@
 // scheduled.
 //
 // Work items are (job, row chunk, group slice).  A persistent grid of
-// 1024-thread workgroups takes items from a queue (one atomic counter) in
+// 512-thread workgroups takes items from a queue (one atomic counter) in
 // the order of a host-made table, largest items first.  An item aggregates
 // its chunk's rows of its slice's groups in LDS with the shared per-tile
 // loop (aggregate_range in slice mode), then either folds them straight
 // into the job's states (the job's only chunk) or writes a partial; the
 // last item of a (job, slice) to finish -- a device-scope counter -- folds
 // all partials of that slice into the states and, when asked, finalises.
+// A job whose groups exceed one workgroup's LDS is, by default, not read
+// once per slice: one item per chunk sorts the chunk's rows by slice into
+// a copy in the workspace (a counting sort: slice counts, then positions),
+// then aggregates each slice from its own rows -- the chunk-local form of
+// the partitioning step of Alg. 4.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -47,16 +52,23 @@ struct BatchJob {
     long long chunk;      // rows per chunk (multiple of the tile)
     long long part_off;   // byte offset of this job's partials in the partial area
     long long spill_off;  // byte offset of its spill array in the spill area (epoch mode), or -1
+    long long scr_off;    // sorted jobs: first row of its sorted copies in the scratch area, else -1
     int G, L, accumulate, vec;
     int nslices, gs, R;   // slices, groups per slice (the last may be smaller), LDS replicas
     int nchunks;
     int done_off;         // first completion counter of this job (one per slice)
-    int pad[1];
+    int gshift;           // sorted jobs: gs = 2^gshift
+    int scr_stride;       // sorted jobs: scratch rows per chunk (its rows and the slices' alignment)
+    int pad;
 };
 
+// slice -1: a sorted item (every slice of the chunk)
 struct BatchItem {
     int job, chunk, slice, pad;
 };
+
+constexpr int SORT_MAX_SLICES = 64;  // slices of a sorted job (LDS counters)
+constexpr int SORT_ALIGN = 8;        // each slice's rows start on a multiple of 8 (vector loads)
 
 // Workspace: [head][jobs][items][counters | spill arrays][partials]; the
 // counters and spill words (zeroed by k_batch_reset) are one contiguous
@@ -71,6 +83,7 @@ struct BatchHead {
     int merge;             // 0: the last item of a (job, slice) merges; 1: a merge launch after the batch
     int nunits;            // merge launch: work units (256 groups of one split job each)
     long long off_units;
+    long long off_scr_keys, off_scr_vals;  // sorted copies: local keys (uint16), values
 };
 
 // A work unit of the merge launch: groups g0 .. g0+255 of a split job.
@@ -80,11 +93,11 @@ struct MergeUnit {
 constexpr int MERGE_UNIT = 256;
 
 struct BatchLayout {
-    size_t jobs, items, units, counters, spill, partials, total;
+    size_t jobs, items, units, counters, spill, partials, scr_keys, scr_vals, total;
 };
 
 inline BatchLayout batch_layout(int njobs, int64_t nitems, int64_t nunits, int64_t ncounters, size_t spill_bytes,
-                                size_t partial_bytes) {
+                                size_t partial_bytes, int64_t scr_rows, size_t vsz) {
     BatchLayout b;
     b.jobs = 256;
     b.items = b.jobs + align_up((size_t)njobs * sizeof(BatchJob), 256);
@@ -92,7 +105,9 @@ inline BatchLayout batch_layout(int njobs, int64_t nitems, int64_t nunits, int64
     b.counters = b.units + align_up((size_t)nunits * sizeof(MergeUnit), 256);
     b.spill = b.counters + align_up((size_t)ncounters * 4, 256);
     b.partials = b.spill + align_up(spill_bytes, 256);
-    b.total = b.partials + align_up(partial_bytes, 256);
+    b.scr_keys = b.partials + align_up(partial_bytes, 256);
+    b.scr_vals = b.scr_keys + align_up((size_t)scr_rows * 2, 256);
+    b.total = b.scr_vals + align_up((size_t)scr_rows * vsz, 256);
     return b;
 }
 
@@ -113,25 +128,16 @@ __device__ __forceinline__ int state_top_of(const AT* S, int g, bool use, int L)
     return use ? state_top(S[g]) : L - 1;
 }
 
-// One item: aggregate, then fold or publish a partial; the last item of a
-// slice folds the slice.  Returns the lane's status bits.
-template <class KT, class VT, class AT, int L, int VEC, bool EPOCH>
-__device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned char* partials, int* counters,
-                             unsigned long long* spill_area, unsigned char* smem, AggShared& sh, int* s_last,
-                             int merge) {
+// After the aggregation of one (chunk, slice) in LDS (bins and tops of Gs
+// groups, R replicas): fold them straight into the states (the job's only
+// chunk) or publish a partial; the last chunk of the slice to finish folds
+// the slice (merge schedule 0).
+template <class AT, int L, bool EPOCH>
+__device__ void finish_slice(const BatchJob& jb, int chunk, int slice, int Gs, int64_t glo, int R,
+                             unsigned char* partials, int* counters, unsigned long long* spill, unsigned char* smem,
+                             int* s_last, int merge) {
     constexpr int NJ = Fmt<AT>::JMAX + 1;
     const int tid = threadIdx.x;
-    const int64_t r0 = (int64_t)bi.chunk * jb.chunk;
-    const int64_t r1 = min((int64_t)jb.n, r0 + jb.chunk);
-    const int64_t glo = (int64_t)bi.slice * jb.gs;
-    const int Gs = (int)min((int64_t)jb.gs, (int64_t)jb.G - glo);
-    const int R = jb.R;
-    // epoch mode (unsliced jobs): rows above a frozen top go to the job's spill array
-    unsigned long long* spill = EPOCH ? spill_area + jb.spill_off / 8 : nullptr;
-    // temporal loads: the items of one chunk's group slices read the same rows
-    const uint32_t err = aggregate_range<KT, VT, AT, L, VEC, EPOCH, true, BATCH_BLOCK, false>(
-        static_cast<const KT*>(jb.keys), static_cast<const VT*>(jb.vals), r0, r1, Gs, R, smem, sh, spill, glo,
-        jb.G);
     long long* bins = reinterpret_cast<long long*>(smem);
     const int2* TOP = reinterpret_cast<const int2*>(bins + (size_t)(Gs + 1) * R * L);
     fold_replicas<L, BATCH_BLOCK>(bins, Gs, R);
@@ -158,13 +164,13 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
             write_group<AT, L>(hi, lo, J, S, C, jb.G, gg, out);
         }
         __syncthreads();  // LDS is reused by the next item
-        return err;
+        return;
     }
     // publish this chunk's partial of the slice
     const size_t pbytes = partial_bytes(jb.gs, L);
-    unsigned char* part0 = partials + jb.part_off + (size_t)bi.slice * jb.nchunks * pbytes;
+    unsigned char* part0 = partials + jb.part_off + (size_t)slice * jb.nchunks * pbytes;
     {
-        unsigned char* pp = part0 + (size_t)bi.chunk * pbytes;
+        unsigned char* pp = part0 + (size_t)chunk * pbytes;
         int* ptop = reinterpret_cast<int*>(pp);
         long long* pK = reinterpret_cast<long long*>(pp + align_up((size_t)jb.gs * 4, 8));
         for (int g = tid; g < Gs; g += BATCH_BLOCK) {
@@ -177,11 +183,11 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
     }
     if (merge) {  // the merge launch after the batch folds the partials
         __syncthreads();  // LDS is reused by the next item
-        return err;
+        return;
     }
     published();  // this thread's partial words (and spill atomics) complete before the count
     __syncthreads();
-    if (tid == 0) *s_last = (atomicAdd(&counters[jb.done_off + bi.slice], 1) == jb.nchunks - 1);
+    if (tid == 0) *s_last = (atomicAdd(&counters[jb.done_off + slice], 1) == jb.nchunks - 1);
     __syncthreads();
     if (*s_last) {
         for (int g = tid; g < Gs; g += BATCH_BLOCK) {
@@ -207,6 +213,121 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
         }
     }
     __syncthreads();
+}
+
+// One (chunk, slice) item: aggregate, then fold or publish.  Returns the
+// lane's status bits.
+template <class KT, class VT, class AT, int L, int VEC, bool EPOCH>
+__device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned char* partials, int* counters,
+                             unsigned long long* spill_area, unsigned char* smem, AggShared& sh, int* s_last,
+                             int merge) {
+    const int64_t r0 = (int64_t)bi.chunk * jb.chunk;
+    const int64_t r1 = min((int64_t)jb.n, r0 + jb.chunk);
+    const int64_t glo = (int64_t)bi.slice * jb.gs;
+    const int Gs = (int)min((int64_t)jb.gs, (int64_t)jb.G - glo);
+    // epoch mode (unsliced jobs): rows above a frozen top go to the job's spill array
+    unsigned long long* spill = EPOCH ? spill_area + jb.spill_off / 8 : nullptr;
+    // temporal loads: the items of one chunk's group slices read the same rows
+    const uint32_t err = aggregate_range<KT, VT, AT, L, VEC, EPOCH, true, BATCH_BLOCK, false>(
+        static_cast<const KT*>(jb.keys), static_cast<const VT*>(jb.vals), r0, r1, Gs, jb.R, smem, sh, spill, glo,
+        jb.G);
+    finish_slice<AT, L, EPOCH>(jb, bi.chunk, bi.slice, Gs, glo, jb.R, partials, counters, spill, smem, s_last, merge);
+    return err;
+}
+
+// A sorted item: every slice of one chunk.  A counting pass takes the rows
+// per slice, a second pass writes each row's local key (key - slice start)
+// and value to its slice's range of the chunk's scratch rows (a row with an
+// unusable value keeps its slot with value +0.0, which contributes nothing;
+// rows with invalid keys are dropped; both set their status bits, as every
+// path does), then each slice is aggregated from its own rows.  Rows land
+// in a slice's range in no fixed order: the level sums are exact.  The
+// scratch rows of a chunk belong to this item alone, and the barrier after
+// the second pass makes its stores visible to the whole workgroup (one CU).
+template <class KT, class VT, class AT, int L>
+__device__ uint32_t run_sorted(const BatchJob& jb, const BatchItem& bi, unsigned char* partials, int* counters,
+                               uint16_t* scr_keys, VT* scr_vals, unsigned char* smem, AggShared& sh, int* s_last,
+                               int merge, int* s_cnt, int* s_cur) {
+    typedef Fmt<AT> Fm;
+    constexpr int U = 8;  // rows in flight per thread
+    constexpr int STEP = U * BATCH_BLOCK;
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)bi.chunk * jb.chunk;
+    const int64_t r1 = min((int64_t)jb.n, r0 + jb.chunk);
+    const KT* keys = static_cast<const KT*>(jb.keys);
+    const VT* vals = static_cast<const VT*>(jb.vals);
+    const uint64_t G = (uint64_t)jb.G;
+    const int sh_g = jb.gshift;
+    const uint32_t gmask = (uint32_t)jb.gs - 1;
+    uint16_t* lk = scr_keys + jb.scr_off + (int64_t)bi.chunk * jb.scr_stride;
+    VT* lv = scr_vals + jb.scr_off + (int64_t)bi.chunk * jb.scr_stride;
+    for (int s = tid; s < jb.nslices; s += BATCH_BLOCK) s_cnt[s] = 0;
+    __syncthreads();
+    // rows per slice (temporal loads: the keys are read again just below)
+    for (int64_t b = r0; b < r1; b += STEP) {
+        KT kk[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = b + u * BATCH_BLOCK + tid;
+            kk[u] = i < r1 ? keys[i] : (KT)-1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if ((uint64_t)(int64_t)kk[u] < G) atomicAdd(&s_cnt[(int)((uint64_t)(int64_t)kk[u] >> sh_g)], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {  // at most SORT_MAX_SLICES: a serial scan
+        int o = 0;
+        for (int s = 0; s < jb.nslices; ++s) {
+            s_cur[s] = o;
+            o += (s_cnt[s] + SORT_ALIGN - 1) / SORT_ALIGN * SORT_ALIGN;
+        }
+    }
+    __syncthreads();
+    uint32_t err = 0;
+    for (int64_t b = r0; b < r1; b += STEP) {
+        KT kk[U];
+        VT vv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = b + u * BATCH_BLOCK + tid;
+            kk[u] = i < r1 ? keys[i] : (KT)0;
+            vv[u] = i < r1 ? __builtin_nontemporal_load(&vals[i]) : (VT)0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = b + u * BATCH_BLOCK + tid;
+            if (i >= r1) continue;
+            VT v = vv[u];
+            if (!finite_val(v)) {
+                err |= ERR_NONFINITE;
+                v = (VT)0;
+            } else if (v != (VT)0 && jreq_raw<AT>(frexp_raw(v)) > Fm::JMAX) {
+                err |= ERR_RANGE;
+                v = (VT)0;
+            }
+            const uint64_t key = (uint64_t)(int64_t)kk[u];
+            if (key < G) {
+                const int pos = atomicAdd(&s_cur[(int)(key >> sh_g)], 1);
+                lk[pos] = (uint16_t)((uint32_t)key & gmask);
+                lv[pos] = v;
+            } else {
+                err |= ERR_KEY;
+            }
+        }
+    }
+    __syncthreads();  // the sorted rows are complete; s_cur[s] is now the end of slice s
+    constexpr int VEC = 16 / sizeof(VT);
+    for (int s = 0; s < jb.nslices; ++s) {
+        const int64_t glo = (int64_t)s << sh_g;
+        const int Gs = (int)min((int64_t)jb.gs, (int64_t)jb.G - glo);
+        const int64_t c1 = s_cur[s];
+        const int64_t c0 = c1 - s_cnt[s];
+        // per-tile mode, no spill array; the values are finite and in the domain, or +0.0
+        aggregate_range<uint16_t, VT, AT, L, VEC, false, false, BATCH_BLOCK, false>(lk, lv, c0, c1, Gs, 1, smem, sh,
+                                                                                     nullptr, 0, 0);
+        finish_slice<AT, L, false>(jb, bi.chunk, s, Gs, glo, 1, partials, counters, nullptr, smem, s_last, merge);
+    }
     return err;
 }
 
@@ -222,6 +343,19 @@ __device__ __forceinline__ uint32_t run_item_vec(const BatchJob& jb, const Batch
     }
     if (jb.vec) return run_item<KT, VT, AT, L, VEC, false>(jb, bi, partials, counters, spill, smem, sh, s_last, merge);
     return run_item<KT, VT, AT, L, 1, false>(jb, bi, partials, counters, spill, smem, sh, s_last, merge);
+}
+
+template <class KT, class VT, class AT>
+__device__ __forceinline__ uint32_t run_sorted_any(const BatchJob& jb, const BatchItem& bi, unsigned char* partials,
+                                                   int* counters, uint16_t* scr_keys, VT* scr_vals,
+                                                   unsigned char* smem, AggShared& sh, int* s_last, int merge,
+                                                   int* s_cnt, int* s_cur) {
+    switch (jb.L) {
+        case 1: return run_sorted<KT, VT, AT, 1>(jb, bi, partials, counters, scr_keys, scr_vals, smem, sh, s_last, merge, s_cnt, s_cur);
+        case 2: return run_sorted<KT, VT, AT, 2>(jb, bi, partials, counters, scr_keys, scr_vals, smem, sh, s_last, merge, s_cnt, s_cur);
+        case 3: return run_sorted<KT, VT, AT, 3>(jb, bi, partials, counters, scr_keys, scr_vals, smem, sh, s_last, merge, s_cnt, s_cur);
+        default: return run_sorted<KT, VT, AT, 4>(jb, bi, partials, counters, scr_keys, scr_vals, smem, sh, s_last, merge, s_cnt, s_cur);
+    }
 }
 
 // The merge launch (merge schedule 1): one 256-thread block per unit, one
@@ -291,12 +425,15 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch(unsigned char* __restrict
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ AggShared sh;
     __shared__ int s_item, s_last;
+    __shared__ int s_cnt[SORT_MAX_SLICES], s_cur[SORT_MAX_SLICES];
     BatchHead* hd = reinterpret_cast<BatchHead*>(ws);
     const BatchJob* jobs = reinterpret_cast<const BatchJob*>(ws + hd->off_jobs);
     const BatchItem* items = reinterpret_cast<const BatchItem*>(ws + hd->off_items);
     int* counters = reinterpret_cast<int*>(ws + hd->off_counters);
     unsigned long long* spill = reinterpret_cast<unsigned long long*>(ws + hd->off_spill);
     unsigned char* partials = ws + hd->off_partials;
+    uint16_t* scr_keys = reinterpret_cast<uint16_t*>(ws + hd->off_scr_keys);
+    VT* scr_vals = reinterpret_cast<VT*>(ws + hd->off_scr_vals);
     const int nitems = hd->nitems;
     const int merge = hd->merge;
     uint32_t err = 0;
@@ -308,6 +445,11 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch(unsigned char* __restrict
         if (it >= nitems) break;
         const BatchItem bi = items[it];
         const BatchJob jb = jobs[bi.job];
+        if (bi.slice < 0) {
+            err |= run_sorted_any<KT, VT, AT>(jb, bi, partials, counters, scr_keys, scr_vals, smem, sh, &s_last, merge,
+                                              s_cnt, s_cur);
+            continue;
+        }
         switch (jb.L) {
             case 1: err |= run_item_vec<KT, VT, AT, 1>(jb, bi, partials, counters, spill, smem, sh, &s_last, merge); break;
             case 2: err |= run_item_vec<KT, VT, AT, 2>(jb, bi, partials, counters, spill, smem, sh, &s_last, merge); break;
@@ -330,6 +472,7 @@ struct HostPlan {
     int64_t ncounters = 0;
     size_t spill_bytes = 0;
     size_t partial_bytes = 0;
+    int64_t scr_rows = 0;  // sorted copies of the chunks of sorted jobs
     size_t lds = 0;
     BatchLayout lay{};
 };
@@ -359,6 +502,8 @@ bool make_batch_plan(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
     if (order != 0 && order != 1) return false;
     const int merge = cfg ? cfg->merge : 0;
     if (merge != 0 && merge != 1) return false;
+    const int split = cfg ? cfg->split : 0;
+    if (split != 0 && split != 1) return false;
     hp->merge = merge;
     hp->units.clear();
     const size_t ksz = kt == REPRO_I64 ? 8 : 4, vsz = scalar_bytes(vt);
@@ -367,6 +512,7 @@ bool make_batch_plan(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
     hp->ncounters = 0;
     hp->spill_bytes = 0;
     hp->partial_bytes = 0;
+    hp->scr_rows = 0;
     const int NJ = (T == REPRO_F64 ? 51 : 14) + 1;  // lattice indices of the accumulator format
     hp->lds = 0;
     std::vector<int64_t> cost;
@@ -389,6 +535,21 @@ bool make_batch_plan(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
         const int cap = slice_cap(u.L, cap_cfg);
         b.nslices = (int)((u.num_groups + cap - 1) / cap);
         b.gs = (int)((u.num_groups + b.nslices - 1) / b.nslices);
+        b.scr_off = -1;
+        bool sorted = false;
+        if (split == 0 && b.nslices > 1) {
+            // sorted: slices of 2^gshift groups (the largest power of two
+            // that fits), at most SORT_MAX_SLICES of them
+            int gshift = 0;
+            while ((2 << gshift) <= cap) ++gshift;
+            const int64_t ns = (u.num_groups + ((int64_t)1 << gshift) - 1) >> gshift;
+            if (ns <= SORT_MAX_SLICES) {
+                sorted = true;
+                b.nslices = (int)ns;
+                b.gs = 1 << gshift;
+                b.gshift = gshift;
+            }
+        }
         b.R = b.nslices == 1 ? replicas_for(b.gs, u.L) : 1;
         hp->lds = std::max(hp->lds, agg_lds_bytes(b.gs, u.L, b.R));
         // chunks: the configured size, larger when the job would need too many;
@@ -416,6 +577,20 @@ bool make_batch_plan(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
             b.part_off = (long long)hp->partial_bytes;
             hp->partial_bytes += align_up((size_t)b.nslices * b.nchunks * partial_bytes(b.gs, u.L), 256);
         }
+        if (sorted) {
+            // one item per chunk; its scratch rows: the chunk's rows plus the
+            // slices' alignment
+            b.scr_stride = (int)(align_up((size_t)std::min<int64_t>(chunk, u.n), SORT_ALIGN) +
+                                 (size_t)SORT_ALIGN * b.nslices);
+            b.scr_off = hp->scr_rows;
+            hp->scr_rows += (int64_t)b.nchunks * b.scr_stride;
+            for (int c = 0; c < b.nchunks; ++c) {
+                hp->items.push_back(BatchItem{j, c, -1, 0});
+                // two passes over the chunk, then its slices' rows once more
+                cost.push_back(3 * std::min<int64_t>(chunk, u.n - (int64_t)c * chunk));
+            }
+            continue;
+        }
         for (int c = 0; c < b.nchunks; ++c)
             for (int s = 0; s < b.nslices; ++s) {
                 hp->items.push_back(BatchItem{j, c, s, 0});
@@ -435,7 +610,7 @@ bool make_batch_plan(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
         hp->items.swap(sorted);
     }
     hp->lay = batch_layout(njobs, (int64_t)hp->items.size(), (int64_t)hp->units.size(), hp->ncounters,
-                           hp->spill_bytes, hp->partial_bytes);
+                           hp->spill_bytes, hp->partial_bytes, hp->scr_rows, vsz);
     return true;
 }
 
@@ -513,6 +688,8 @@ int plan_into(const repro_batch_job* jobs, int njobs, repro_key_t kt, repro_scal
     hd.merge = hp.merge;
     hd.nunits = (int)hp.units.size();
     hd.off_units = (long long)hp.lay.units;
+    hd.off_scr_keys = (long long)hp.lay.scr_keys;
+    hd.off_scr_vals = (long long)hp.lay.scr_vals;
     memcpy(img, &hd, sizeof(hd));
     if (njobs) memcpy(img + hp.lay.jobs, hp.jobs.data(), hp.jobs.size() * sizeof(BatchJob));
     if (!hp.items.empty()) memcpy(img + hp.lay.items, hp.items.data(), hp.items.size() * sizeof(BatchItem));
@@ -580,6 +757,7 @@ int repro_batch_tune(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
     const int caps[] = {0, 1024};
     const int orders[] = {0, 1};
     const int merges[] = {0, 1};
+    const int splits[] = {0, 1};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return REPRO_EHIP;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -591,8 +769,9 @@ int repro_batch_tune(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
     for (int64_t ch : chunks)
         for (int cap : caps)
             for (int ord : orders)
-                for (int mg : merges) {
-                repro_batch_config c{ch, cap, ord, mg};
+                for (int mg : merges)
+                    for (int sp : splits) {
+                repro_batch_config c{ch, cap, ord, mg, sp};
                 if (repro_batch_workspace_bytes(jobs, njobs, kt, vt, T, &c) > workspace_bytes) continue;
                 repro_batch_plan p;
                 rc = repro_batch_prepare(jobs, njobs, kt, vt, T, &c, workspace, workspace_bytes, &p, stream);

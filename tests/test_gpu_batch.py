@@ -102,7 +102,8 @@ def test_batch_matches_oracle_per_job(config):
 @pytest.mark.parametrize("config", [
     {"chunk_rows": 8192}, {"chunk_rows": 1 << 20}, {"max_slice_groups": 300}, {"order": 1},
     {"chunk_rows": 16384, "max_slice_groups": 1000, "order": 1}, {"merge": 1}, {"chunk_rows": 8192, "merge": 1},
-    {"chunk_rows": 16384, "max_slice_groups": 300, "order": 1, "merge": 1}])
+    {"chunk_rows": 16384, "max_slice_groups": 300, "order": 1, "merge": 1},
+    {"split": 1}, {"split": 1, "chunk_rows": 8192, "merge": 1}, {"split": 1, "max_slice_groups": 300, "order": 1}])
 def test_batch_configuration_does_not_change_bits(config):
     specs = mixed_jobs(2, 24, max_rows=200_000, errors=False)
     say(f"case batch config {config}")
@@ -116,6 +117,56 @@ def test_batch_configuration_does_not_change_bits(config):
     torch.cuda.synchronize()
     for a, j in zip(before, jobs):
         assert torch.equal(a, j.states)
+
+
+@pytest.mark.parametrize("split,merge", [(0, 0), (0, 1), (1, 0)])
+def test_batch_sorted_slices_status_and_edges(split, merge):
+    """Jobs beyond one workgroup's LDS, run with their chunks sorted by group
+    slice (split 0) or read once per slice (split 1): status bits when the
+    only NaN, Inf and out-of-domain values sit on rows with invalid keys,
+    and separately on rows with valid keys; a job whose rows all fall in
+    one slice; the last slice shorter than the others; several chunks.
+    States, sums and status equal the oracle's."""
+    rng = np.random.default_rng([11, split, merge])
+    specs = []
+    G = 20_000
+    # only the bad-key rows hold unusable values: KEY | NONFINITE | RANGE
+    n = 70_000
+    keys = rng.integers(0, G, n).astype(np.int32)
+    vals = np.ldexp(rng.standard_normal(n), rng.integers(-30, 31, n))
+    keys[[7, 900, 50_000]] = [G, -1, G + 99]
+    vals[[7, 900, 50_000]] = [np.nan, np.inf, 1.7e308]
+    specs.append((keys, vals, G, 2))
+    # valid keys with NaN / -Inf values: NONFINITE only
+    keys2 = rng.integers(0, 9_000, 40_000).astype(np.int32)
+    vals2 = rng.standard_normal(40_000)
+    vals2[[3, 30_001]] = [np.nan, -np.inf]
+    specs.append((keys2, vals2, 9_000, 3))
+    # every row in the last slice, which is shorter than the others
+    G3 = 3 * 4096 + 5
+    keys3 = rng.integers(3 * 4096, G3, 30_000).astype(np.int32)
+    specs.append((keys3, np.ldexp(rng.standard_normal(30_000), rng.integers(-60, 61, 30_000)), G3, 1))
+    # many slices, many chunks, cancelling pairs
+    G4 = 60_000
+    half = rng.standard_normal(100_000) * 2.0 ** 40
+    keys4 = np.concatenate([rng.integers(0, G4, 100_000)] * 2).astype(np.int32)
+    specs.append((keys4, np.concatenate([half, -half]), G4, 4))
+    # no rows at all
+    specs.append((np.zeros(0, np.int32), np.zeros(0), 30_000, 2))
+    jobs, priors = make_batch(specs, accumulate=lambda i: i == 1)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    config = {"split": split, "merge": merge, "chunk_rows": 16384}
+    say(f"case sorted slices {config}")
+    api.batch_groupby_sum(jobs, config=config, status=status)
+    torch.cuda.synchronize()
+    check_jobs(jobs, specs, priors, int(status.item()), f"sorted slices {config}")
+    assert int(status.item()) == 7  # KEY | NONFINITE | RANGE
+    # the status word of the first job alone, against the oracle's
+    status.zero_()
+    only, _ = make_batch(specs[:1])
+    api.batch_groupby_sum(only, config=config, status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == O.groupby_sum(*specs[0])[1] == 7
 
 
 def test_batch_accumulating_launches_add_the_batch_each_time():
