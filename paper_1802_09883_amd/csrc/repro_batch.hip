@@ -216,9 +216,10 @@ __device__ void finish_slice(const BatchJob& jb, int chunk, int slice, int Gs, i
 }
 
 // One (chunk, slice) item: aggregate, then fold or publish.  Returns the
-// lane's status bits.
-template <class KT, class VT, class AT, int L, int VEC, bool EPOCH>
-__device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned char* partials, int* counters,
+// lane's status bits.  SLICE: the job is cut into group slices (the rows of
+// other slices are skipped); a job in one slice takes the unsliced loop.
+template <class KT, class VT, class AT, int L, int VEC, bool EPOCH, bool SLICE>
+__device__ __attribute__((noinline)) uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned char* partials, int* counters,
                              unsigned long long* spill_area, unsigned char* smem, AggShared& sh, int* s_last,
                              int merge) {
     const int64_t r0 = (int64_t)bi.chunk * jb.chunk;
@@ -228,7 +229,7 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
     // epoch mode (unsliced jobs): rows above a frozen top go to the job's spill array
     unsigned long long* spill = EPOCH ? spill_area + jb.spill_off / 8 : nullptr;
     // temporal loads: the items of one chunk's group slices read the same rows
-    const uint32_t err = aggregate_range<KT, VT, AT, L, VEC, EPOCH, true, BATCH_BLOCK, false>(
+    const uint32_t err = aggregate_range<KT, VT, AT, L, VEC, EPOCH, SLICE, BATCH_BLOCK, false>(
         static_cast<const KT*>(jb.keys), static_cast<const VT*>(jb.vals), r0, r1, Gs, jb.R, smem, sh, spill, glo,
         jb.G);
     finish_slice<AT, L, EPOCH>(jb, bi.chunk, bi.slice, Gs, glo, jb.R, partials, counters, spill, smem, s_last, merge);
@@ -244,13 +245,27 @@ __device__ uint32_t run_item(const BatchJob& jb, const BatchItem& bi, unsigned c
 // in a slice's range in no fixed order: the level sums are exact.  The
 // scratch rows of a chunk belong to this item alone, and the barrier after
 // the second pass makes its stores visible to the whole workgroup (one CU).
+//
+// Atomics of many lanes on one LDS address serialise, so the counting pass
+// spreads its counters over SORT_REP replicas (replica = thread index mod
+// SORT_REP, stride SORT_REP_STRIDE words).  The second pass takes positions
+// from one cursor per slice, so the rows of a wave's store instruction fall
+// into few runs (spreading the cursors as well scattered the stores, and a
+// wave-level ranking by ballots was slower than the serialised atomics).
+// The counters live in the bin area of LDS, which the passes do not use.
+constexpr int SORT_REP = 16;
+constexpr int SORT_REP_STRIDE = SORT_MAX_SLICES + 1;  // odd: replicas of a slice in different banks
+
 template <class KT, class VT, class AT, int L>
-__device__ uint32_t run_sorted(const BatchJob& jb, const BatchItem& bi, unsigned char* partials, int* counters,
-                               uint16_t* scr_keys, VT* scr_vals, unsigned char* smem, AggShared& sh, int* s_last,
-                               int merge, int* s_cnt, int* s_cur) {
+__device__ __attribute__((noinline)) uint32_t run_sorted(const BatchJob& jb, const BatchItem& bi,
+                                                         unsigned char* partials, int* counters, uint16_t* scr_keys,
+                                                         VT* scr_vals, unsigned char* smem, AggShared& sh,
+                                                         int* s_last, int merge, int* s_cnt, int* s_off) {
     typedef Fmt<AT> Fm;
-    constexpr int U = 8;  // rows in flight per thread
-    constexpr int STEP = U * BATCH_BLOCK;
+    // rows in flight per thread (no barrier inside either pass: the waves
+    // overlap their loads); a workgroup keeps 64-96 KiB of loads in flight
+    constexpr int UC = 32, U = 16;
+    constexpr int NREP = SORT_REP * SORT_REP_STRIDE;
     const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)bi.chunk * jb.chunk;
     const int64_t r1 = min((int64_t)jb.n, r0 + jb.chunk);
@@ -258,34 +273,46 @@ __device__ uint32_t run_sorted(const BatchJob& jb, const BatchItem& bi, unsigned
     const VT* vals = static_cast<const VT*>(jb.vals);
     const uint64_t G = (uint64_t)jb.G;
     const int sh_g = jb.gshift;
+    const int ns = jb.nslices;
     const uint32_t gmask = (uint32_t)jb.gs - 1;
     uint16_t* lk = scr_keys + jb.scr_off + (int64_t)bi.chunk * jb.scr_stride;
     VT* lv = scr_vals + jb.scr_off + (int64_t)bi.chunk * jb.scr_stride;
-    for (int s = tid; s < jb.nslices; s += BATCH_BLOCK) s_cnt[s] = 0;
+    int* rcnt = reinterpret_cast<int*>(smem);  // [SORT_REP][SORT_REP_STRIDE]
+    int* cur = rcnt + NREP;                    // [SORT_MAX_SLICES]: next row of each slice
+    int* my_cnt = rcnt + (tid % SORT_REP) * SORT_REP_STRIDE;
+    for (int k = tid; k < NREP; k += BATCH_BLOCK) rcnt[k] = 0;
     __syncthreads();
-    // rows per slice (temporal loads: the keys are read again just below)
-    for (int64_t b = r0; b < r1; b += STEP) {
-        KT kk[U];
+    // rows per (replica, slice) (temporal loads: the keys are read again below)
+    for (int64_t b = r0; b < r1; b += (int64_t)UC * BATCH_BLOCK) {
+        KT kk[UC];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < UC; ++u) {
             const int64_t i = b + u * BATCH_BLOCK + tid;
             kk[u] = i < r1 ? keys[i] : (KT)-1;
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if ((uint64_t)(int64_t)kk[u] < G) atomicAdd(&s_cnt[(int)((uint64_t)(int64_t)kk[u] >> sh_g)], 1);
+        for (int u = 0; u < UC; ++u)
+            if ((uint64_t)(int64_t)kk[u] < G) atomicAdd(&my_cnt[(int)((uint64_t)(int64_t)kk[u] >> sh_g)], 1);
     }
     __syncthreads();
-    if (tid == 0) {  // at most SORT_MAX_SLICES: a serial scan
+    for (int s = tid; s < ns; s += BATCH_BLOCK) {
+        int c = 0;
+        for (int r = 0; r < SORT_REP; ++r) c += rcnt[r * SORT_REP_STRIDE + s];
+        s_cnt[s] = c;
+    }
+    __syncthreads();
+    if (tid == 0) {  // at most SORT_MAX_SLICES: a serial scan; slices start on multiples of SORT_ALIGN
         int o = 0;
-        for (int s = 0; s < jb.nslices; ++s) {
-            s_cur[s] = o;
+        for (int s = 0; s < ns; ++s) {
+            s_off[s] = o;
             o += (s_cnt[s] + SORT_ALIGN - 1) / SORT_ALIGN * SORT_ALIGN;
         }
     }
     __syncthreads();
+    for (int k = tid; k < ns; k += BATCH_BLOCK) cur[k] = s_off[k];
+    __syncthreads();
     uint32_t err = 0;
-    for (int64_t b = r0; b < r1; b += STEP) {
+    for (int64_t b = r0; b < r1; b += (int64_t)U * BATCH_BLOCK) {
         KT kk[U];
         VT vv[U];
 #pragma unroll
@@ -297,35 +324,38 @@ __device__ uint32_t run_sorted(const BatchJob& jb, const BatchItem& bi, unsigned
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t i = b + u * BATCH_BLOCK + tid;
-            if (i >= r1) continue;
+            int sl = -1;  // slice of the row, -1: no row or an invalid key
             VT v = vv[u];
-            if (!finite_val(v)) {
-                err |= ERR_NONFINITE;
-                v = (VT)0;
-            } else if (v != (VT)0 && jreq_raw<AT>(frexp_raw(v)) > Fm::JMAX) {
-                err |= ERR_RANGE;
-                v = (VT)0;
-            }
             const uint64_t key = (uint64_t)(int64_t)kk[u];
-            if (key < G) {
-                const int pos = atomicAdd(&s_cur[(int)(key >> sh_g)], 1);
+            if (i < r1) {
+                if (!finite_val(v)) {
+                    err |= ERR_NONFINITE;
+                    v = (VT)0;
+                } else if (v != (VT)0 && jreq_raw<AT>(frexp_raw(v)) > Fm::JMAX) {
+                    err |= ERR_RANGE;
+                    v = (VT)0;
+                }
+                if (key < G)
+                    sl = (int)(key >> sh_g);
+                else
+                    err |= ERR_KEY;
+            }
+            const int pos = sl >= 0 ? atomicAdd(&cur[sl], 1) : 0;
+            if (sl >= 0) {
                 lk[pos] = (uint16_t)((uint32_t)key & gmask);
                 lv[pos] = v;
-            } else {
-                err |= ERR_KEY;
             }
         }
     }
-    __syncthreads();  // the sorted rows are complete; s_cur[s] is now the end of slice s
+    __syncthreads();  // the sorted rows are complete; the bin area is free again
     constexpr int VEC = 16 / sizeof(VT);
-    for (int s = 0; s < jb.nslices; ++s) {
+    for (int s = 0; s < ns; ++s) {
         const int64_t glo = (int64_t)s << sh_g;
         const int Gs = (int)min((int64_t)jb.gs, (int64_t)jb.G - glo);
-        const int64_t c1 = s_cur[s];
-        const int64_t c0 = c1 - s_cnt[s];
+        const int64_t c0 = s_off[s];
         // per-tile mode, no spill array; the values are finite and in the domain, or +0.0
-        aggregate_range<uint16_t, VT, AT, L, VEC, false, false, BATCH_BLOCK, false>(lk, lv, c0, c1, Gs, 1, smem, sh,
-                                                                                     nullptr, 0, 0);
+        aggregate_range<uint16_t, VT, AT, L, VEC, false, false, BATCH_BLOCK, false>(lk, lv, c0, c0 + s_cnt[s], Gs, 1,
+                                                                                     smem, sh, nullptr, 0, 0);
         finish_slice<AT, L, false>(jb, bi.chunk, s, Gs, glo, 1, partials, counters, nullptr, smem, s_last, merge);
     }
     return err;
@@ -336,25 +366,32 @@ __device__ __forceinline__ uint32_t run_item_vec(const BatchJob& jb, const Batch
                                                  int* counters, unsigned long long* spill, unsigned char* smem,
                                                  AggShared& sh, int* s_last, int merge) {
     constexpr int VEC = 16 / sizeof(VT);
+    // epoch mode (a spill array) only for jobs in one slice
     if (jb.spill_off >= 0) {
         if (jb.vec)
-            return run_item<KT, VT, AT, L, VEC, true>(jb, bi, partials, counters, spill, smem, sh, s_last, merge);
-        return run_item<KT, VT, AT, L, 1, true>(jb, bi, partials, counters, spill, smem, sh, s_last, merge);
+            return run_item<KT, VT, AT, L, VEC, true, false>(jb, bi, partials, counters, spill, smem, sh, s_last, merge);
+        return run_item<KT, VT, AT, L, 1, true, false>(jb, bi, partials, counters, spill, smem, sh, s_last, merge);
     }
-    if (jb.vec) return run_item<KT, VT, AT, L, VEC, false>(jb, bi, partials, counters, spill, smem, sh, s_last, merge);
-    return run_item<KT, VT, AT, L, 1, false>(jb, bi, partials, counters, spill, smem, sh, s_last, merge);
+    if (jb.nslices == 1) {
+        if (jb.vec)
+            return run_item<KT, VT, AT, L, VEC, false, false>(jb, bi, partials, counters, spill, smem, sh, s_last, merge);
+        return run_item<KT, VT, AT, L, 1, false, false>(jb, bi, partials, counters, spill, smem, sh, s_last, merge);
+    }
+    if (jb.vec)
+        return run_item<KT, VT, AT, L, VEC, false, true>(jb, bi, partials, counters, spill, smem, sh, s_last, merge);
+    return run_item<KT, VT, AT, L, 1, false, true>(jb, bi, partials, counters, spill, smem, sh, s_last, merge);
 }
 
 template <class KT, class VT, class AT>
 __device__ __forceinline__ uint32_t run_sorted_any(const BatchJob& jb, const BatchItem& bi, unsigned char* partials,
                                                    int* counters, uint16_t* scr_keys, VT* scr_vals,
                                                    unsigned char* smem, AggShared& sh, int* s_last, int merge,
-                                                   int* s_cnt, int* s_cur) {
+                                                   int* s_cnt, int* s_off) {
     switch (jb.L) {
-        case 1: return run_sorted<KT, VT, AT, 1>(jb, bi, partials, counters, scr_keys, scr_vals, smem, sh, s_last, merge, s_cnt, s_cur);
-        case 2: return run_sorted<KT, VT, AT, 2>(jb, bi, partials, counters, scr_keys, scr_vals, smem, sh, s_last, merge, s_cnt, s_cur);
-        case 3: return run_sorted<KT, VT, AT, 3>(jb, bi, partials, counters, scr_keys, scr_vals, smem, sh, s_last, merge, s_cnt, s_cur);
-        default: return run_sorted<KT, VT, AT, 4>(jb, bi, partials, counters, scr_keys, scr_vals, smem, sh, s_last, merge, s_cnt, s_cur);
+        case 1: return run_sorted<KT, VT, AT, 1>(jb, bi, partials, counters, scr_keys, scr_vals, smem, sh, s_last, merge, s_cnt, s_off);
+        case 2: return run_sorted<KT, VT, AT, 2>(jb, bi, partials, counters, scr_keys, scr_vals, smem, sh, s_last, merge, s_cnt, s_off);
+        case 3: return run_sorted<KT, VT, AT, 3>(jb, bi, partials, counters, scr_keys, scr_vals, smem, sh, s_last, merge, s_cnt, s_off);
+        default: return run_sorted<KT, VT, AT, 4>(jb, bi, partials, counters, scr_keys, scr_vals, smem, sh, s_last, merge, s_cnt, s_off);
     }
 }
 
@@ -425,7 +462,7 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch(unsigned char* __restrict
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ AggShared sh;
     __shared__ int s_item, s_last;
-    __shared__ int s_cnt[SORT_MAX_SLICES], s_cur[SORT_MAX_SLICES];
+    __shared__ int s_cnt[SORT_MAX_SLICES], s_off[SORT_MAX_SLICES];
     BatchHead* hd = reinterpret_cast<BatchHead*>(ws);
     const BatchJob* jobs = reinterpret_cast<const BatchJob*>(ws + hd->off_jobs);
     const BatchItem* items = reinterpret_cast<const BatchItem*>(ws + hd->off_items);
@@ -447,7 +484,7 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch(unsigned char* __restrict
         const BatchJob jb = jobs[bi.job];
         if (bi.slice < 0) {
             err |= run_sorted_any<KT, VT, AT>(jb, bi, partials, counters, scr_keys, scr_vals, smem, sh, &s_last, merge,
-                                              s_cnt, s_cur);
+                                              s_cnt, s_off);
             continue;
         }
         switch (jb.L) {
@@ -584,6 +621,8 @@ bool make_batch_plan(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
                                  (size_t)SORT_ALIGN * b.nslices);
             b.scr_off = hp->scr_rows;
             hp->scr_rows += (int64_t)b.nchunks * b.scr_stride;
+            // the slice counters use the bin area during the passes
+            hp->lds = std::max(hp->lds, (SORT_REP * SORT_REP_STRIDE + SORT_MAX_SLICES) * sizeof(int));
             for (int c = 0; c < b.nchunks; ++c) {
                 hp->items.push_back(BatchItem{j, c, -1, 0});
                 // two passes over the chunk, then its slices' rows once more
