@@ -105,11 +105,16 @@ def main():
     ap.add_argument("--stream-ceiling", action="store_true",
                     help="only measure the read-stream ceiling: a plain read kernel over the low-cardinality "
                          "workload's bytes, swept over launch shapes")
+    ap.add_argument("--atomic-ceiling", action="store_true",
+                    help="only measure global 64-bit atomic adds: uniform indices over the 64 MiB of level words "
+                         "of the high-cardinality workload, and that workload's Zipf keys")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
     if args.stream_ceiling:
         return stream_ceiling(args)
+    if args.atomic_ceiling:
+        return atomic_ceiling(args)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -634,6 +639,59 @@ def stream_ceiling(args):
     agg_shape = next(r for r in res if r["workgroups"] == 256 and r["threads"] == 1024)
     print(json.dumps({"metric": "read-stream ceiling", "bytes": nbytes, "steps": args.steps, "best": best,
                       "aggregation_launch_shape": agg_shape, "peak_GB/s": HBM_PEAK_GBS, "sweep": res}), flush=True)
+
+
+def atomic_ceiling(args):
+    """Global-atomic rate (repro_atomic_probe): 1e8 64-bit atomic adds with
+    uniform indices over 2^23 words (the 64 MiB of int64 level words of
+    2^22 groups at L = 2, which fit the Infinity Cache), then with the
+    high-cardinality workload's Zipf(1) keys over 2^22 words.  Aggregating
+    that workload's level units with global atomics needs L = 2 such adds
+    per row (after a pass for the tops), so 2x the uniform time is a lower
+    bound for it, to compare with the partitioned step."""
+    import ctypes
+
+    import torch
+
+    from paper_1802_09883_amd import _lib, workloads
+
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+    cfg = CONFIGS["highcard"]
+    n, G = cfg["rows"], cfg["groups"]
+    stream = torch.cuda.current_stream(dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    uni = torch.randint(0, 2 * G, (n,), generator=gen, dtype=torch.int32, device=dev)
+    keys, _ = workloads.highcard(n=n, groups=G)
+    zipf = torch.from_numpy(keys.astype(np.int32)).to(dev)
+    del keys
+    table = torch.zeros(2 * G, dtype=torch.int64, device=dev)
+    res = {}
+    for name, idx, words in (("uniform_64MiB", uni, 2 * G), ("zipf_keys", zipf, G)):
+        def launch():
+            _lib.check(lib.repro_atomic_probe(ctypes.c_void_p(idx.data_ptr()), n, ctypes.c_void_p(table.data_ptr()),
+                                              words, 4096, ctypes.c_void_p(stream.cuda_stream)), "atomic_probe")
+        launch()
+        torch.cuda.synchronize()
+        reps = max(1, min(args.steps, 5))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            launch()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = {"atomics": n, "ms": round(ms, 4), "G_atomics_per_s": round(n / (ms * 1e-3) / 1e9, 2)}
+        log(f"{name}: {n} atomics in {ms:.3f} ms ({res[name]['G_atomics_per_s']} G/s)")
+    total = int(table.sum().item())
+    if total != n * (1 + reps) * 2:
+        raise SystemExit(f"atomic probe lost adds: {total} != {n * (1 + reps) * 2}")
+    print(json.dumps({"metric": "global-atomic ceiling", "workgroups": 4096, "threads": 256, **res,
+                      "level_adds_per_row": 2,
+                      "atomic_groupby_lower_bound_ms": {"uniform": round(2 * res["uniform_64MiB"]["ms"], 3),
+                                                        "zipf_keys": round(2 * res["zipf_keys"]["ms"], 3)}}),
+          flush=True)
 
 
 def copy_calibration(nbytes):

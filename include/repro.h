@@ -430,6 +430,18 @@ int repro_profile_read(float* ms, int cap, int* count);
 int repro_read_probe(const void* data, size_t bytes, int workgroups, int threads, unsigned long long* sink,
                      hipStream_t stream);
 
+/*
+ * Measurement aid: one 64-bit device-scope atomic add per index,
+ * table[idx[i]] += 1 for i < n (idx: device int32; table: device uint64 of
+ * table_words entries; an index outside [0, table_words) is skipped), on a
+ * grid of `workgroups` x 256 threads.  Its rate is that of global atomics
+ * on a working set of table_words * 8 bytes (e.g. the Infinity Cache), the
+ * bound of aggregating level words with global atomics instead of
+ * partitioning into LDS.
+ */
+int repro_atomic_probe(const int32_t* idx, int64_t n, unsigned long long* table, int64_t table_words,
+                       int workgroups, hipStream_t stream);
+
 /* Library version string. */
 const char* repro_version(void);
 

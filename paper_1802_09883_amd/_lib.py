@@ -133,6 +133,8 @@ def load():
     lib.repro_groupby_sum_noalloc.argtypes = [vp, i32, vp, i32, i64, i64, i32, i32, vp, vp, vp]
     lib.repro_read_probe.restype = ctypes.c_int
     lib.repro_read_probe.argtypes = [vp, sz, i32, i32, vp, vp]
+    lib.repro_atomic_probe.restype = ctypes.c_int
+    lib.repro_atomic_probe.argtypes = [vp, i64, vp, i64, i32, vp]
     lib.repro_version.restype = ctypes.c_char_p
     lib.repro_version.argtypes = []
     for name in ("repro_state_init", "repro_groupby_sum", "repro_merge", "repro_finalize",

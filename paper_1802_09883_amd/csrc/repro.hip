@@ -668,6 +668,15 @@ __global__ void k_read_probe(const u32x4* __restrict__ p, size_t words, unsigned
     if (any && threadIdx.x == 0) atomicAdd(sink, 1ull);
 }
 
+__global__ void __launch_bounds__(256) k_atomic_probe(const int* __restrict__ idx, int64_t n,
+                                                      unsigned long long* __restrict__ table, int64_t words) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        const int j = idx[i];
+        if ((uint64_t)(int64_t)j < (uint64_t)words) atomicAdd(&table[j], 1ull);
+    }
+}
+
 // ================================================================ host
 
 inline size_t scalar_size(repro_scalar_t t) { return t == REPRO_F64 ? 8 : 4; }
@@ -1223,6 +1232,15 @@ int repro_read_probe(const void* data, size_t bytes, int workgroups, int threads
         return REPRO_EINVAL;
     hipLaunchKernelGGL(k_read_probe, dim3(workgroups), dim3(threads), 0, stream, static_cast<const u32x4*>(data),
                        bytes / 16, sink);
+    LAUNCH_CHECK();
+    return REPRO_OK;
+}
+
+int repro_atomic_probe(const int32_t* idx, int64_t n, unsigned long long* table, int64_t table_words,
+                       int workgroups, hipStream_t stream) {
+    if (n < 0 || table_words < 1 || workgroups < 1 || (n > 0 && (!idx || !table))) return REPRO_EINVAL;
+    if (n == 0) return REPRO_OK;
+    hipLaunchKernelGGL(k_atomic_probe, dim3(workgroups), dim3(256), 0, stream, idx, n, table, table_words);
     LAUNCH_CHECK();
     return REPRO_OK;
 }

@@ -107,6 +107,11 @@ def test_plain_baseline_workspace_and_probe_checks(lib):
     assert lib.repro_read_probe(p, 1024, 4, 100, p, null) == _lib.REPRO_EINVAL
     assert lib.repro_read_probe(p, 1000, 4, 256, p, null) == _lib.REPRO_EINVAL
     assert lib.repro_read_probe(null, 1024, 4, 256, p, null) == _lib.REPRO_EINVAL
+    assert lib.repro_atomic_probe(p, 10, p, 0, 4, null) == _lib.REPRO_EINVAL
+    assert lib.repro_atomic_probe(p, 10, p, 16, 0, null) == _lib.REPRO_EINVAL
+    assert lib.repro_atomic_probe(null, 10, p, 16, 4, null) == _lib.REPRO_EINVAL
+    assert lib.repro_atomic_probe(p, -1, p, 16, 4, null) == _lib.REPRO_EINVAL
+    assert lib.repro_atomic_probe(null, 0, null, 16, 4, null) == _lib.REPRO_OK  # nothing to do
 
 
 def _jobs(specs):
