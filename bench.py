@@ -202,11 +202,12 @@ def main():
     log(f"step {ms_step:.3f} ms; aggregation kernel " +
         ", ".join(f"{name} {np.mean(k):.3f} ms" for name, k in zip(knames, kcol)))
 
-    # inputs small enough to stay in the 256 MB Infinity Cache between steps:
-    # also time single steps after streaming 1 GiB through the caches (cold)
+    # inputs small enough to stay in the 256 MB Infinity Cache between steps,
+    # and the partitioned path (whose states and partition buffers may stay in
+    # it): also time single steps after streaming 1 GiB through the caches (cold)
     cold_ms = None
     in_bytes = kt.numel() * kt.element_size() + sum(v.numel() * v.element_size() for _, v in vts)
-    if in_bytes < (512 << 20):
+    if in_bytes < (512 << 20) or args.config == "highcard":
         flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         cold = []
         for _ in range(args.steps):
