@@ -753,9 +753,29 @@ def cpu_baseline(keys, cols, G, L, seconds, T64=True):
     for _ in range(reps):
         run(m)
     dt = time.perf_counter() - t0
-    return {"value": reps * m / dt, "unit": "rows/s", "cores": cores, "kind": "oracle", "host": host,
+    rate = reps * m / dt
+    # beside it, on a prefix of about a second's work: the oracle on one
+    # thread, and a plain (non-reproducible) FP64 GroupBy-SUM on one thread
+    # (numpy bincount with weights), both over every column
+    m1 = int(min(len(keys), max(10 ** 5, rate / max(cores, 1))))
+    t0 = time.perf_counter()
+    for v in cols:
+        st, _ = oracle.groupby_sum(keys[:m1], v[:m1], G, L, T64, threads=1)
+        oracle.finalize(st, G, L, T64)
+    one = m1 / (time.perf_counter() - t0)
+    k1 = keys[:m1].astype(np.int64)
+    t0 = time.perf_counter()
+    for v in cols:
+        np.bincount(k1, weights=v[:m1].astype(np.float64), minlength=G)
+    plain1 = m1 / (time.perf_counter() - t0)
+    log(f"cpu oracle {rate:.3e} rows/s on {cores} threads, {one:.3e} on one; plain FP64 {plain1:.3e} on one")
+    return {"value": rate, "unit": "rows/s", "cores": cores, "kind": "oracle", "host": host,
             "sample": f"{reps} pass(es) over the first {m} rows (of {len(keys)}) of all {len(cols)} column(s), "
-                      f"{cores} threads, {dt:.1f} s"}
+                      f"{cores} threads, {dt:.1f} s",
+            "ns_per_row_per_core": round(cores * 1e9 / rate, 2),
+            "one_thread": {"oracle_rows_per_s": one, "plain_fp64_rows_per_s": plain1,
+                           "oracle_over_plain": round(plain1 / one, 2), "rows": m1,
+                           "plain": "numpy bincount with float64 weights"}}
 
 
 if __name__ == "__main__":
