@@ -463,8 +463,11 @@ def bench_serve(args):
     from paper_1802_09883_amd import api, workloads
 
     Q = 128
-    slots = int(os.environ.get("REPRO_SERVE_SLOTS", "8"))
+    # defaults from a sweep of slots x workgroup cap x chunk rows on this
+    # workload: 4 slots and 64M-row chunks gave the lowest p99 at 70% load
+    slots = int(os.environ.get("REPRO_SERVE_SLOTS", "4"))
     max_bypass = int(os.environ.get("REPRO_SERVE_BYPASS", "8"))
+    chunk_rows = int(os.environ.get("REPRO_SERVE_CHUNK", str(64 << 20)))
     rows, groups, gaps = workloads.served_queries(Q)
     n_all = int(rows.sum())
     log(f"generating {Q} queries, {n_all} rows")
@@ -485,7 +488,7 @@ def bench_serve(args):
     qwg = int(os.environ.get("REPRO_QUERY_WG", "0"))  # persistent workgroups per query (0: all)
 
     def run(arrivals):
-        srv = api.Server(arena, slots=slots, query_workgroups=qwg, max_bypass=max_bypass)
+        srv = api.Server(arena, slots=slots, query_workgroups=qwg, max_bypass=max_bypass, chunk_rows=chunk_rows)
         try:
             t0 = srv.clock()
             arr = t0 + arrivals
@@ -537,7 +540,7 @@ def bench_serve(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": CONFIGS["serve"]["desc"].format(q=Q, n=n_all, slots=slots), "name": "serve",
                    "queries": Q, "rows": n_all, "slots": slots, "max_bypass": max_bypass,
-                   "query_workgroups": qwg, "parallelism": "single GPU"},
+                   "query_workgroups": qwg, "chunk_rows": chunk_rows, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4), "mean": round(float(np.mean(lat)) * 1e3, 4),
                        "offered_rate_qps": round(rate, 2), "open_loop_rows_per_s": n_all / span_o},
         "step_hbm_frac": round(ach / HBM_PEAK_GBS, 4),
