@@ -243,8 +243,10 @@ __global__ void __launch_bounds__(PART_BLOCK) k_part_plan(const long long* __res
 
 // Exclusive scan of cnt[0..F) into off[0..F) by one 1024-thread block
 // (F <= 4096: up to 4 consecutive entries per thread, wave scans, LDS for
-// the wave totals).  Returns the total.  Contains barriers.
-__device__ __forceinline__ int block_exclusive_scan(const int* cnt, int* off, int F, int* wsum) {
+// the wave totals).  Returns the total.  Contains barriers.  When `base` is
+// given, base[p] -= off[p] as well (by the thread that writes off[p]).
+__device__ __forceinline__ int block_exclusive_scan(const int* cnt, int* off, int F, int* wsum,
+                                                    long long* base = nullptr) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int per = (F + PART_BLOCK - 1) / PART_BLOCK;
     const int p0 = min(F, t * per), p1 = min(F, p0 + per);
@@ -266,6 +268,7 @@ __device__ __forceinline__ int block_exclusive_scan(const int* cnt, int* off, in
     int run = before + inc - local;
     for (int p = p0; p < p1; ++p) {
         off[p] = run;
+        if (base) base[p] -= run;
         run += cnt[p];
     }
     __syncthreads();
@@ -341,7 +344,10 @@ __global__ void __launch_bounds__(PART_BLOCK)
             }
         }
         __syncthreads();  // all tile counts in place
-        const int ntile = block_exclusive_scan(cnt, off, F, wsum);
+        // off: the partitions' offsets in the tile; cur[p] becomes the slot of
+        // the tile's first row of p minus off[p], so a staged row j of p goes
+        // to slot cur[p] + j (one LDS read fewer per row when writing out)
+        const int ntile = block_exclusive_scan(cnt, off, F, wsum, cur);
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             if (pi[u] >= 0) {
@@ -352,14 +358,18 @@ __global__ void __launch_bounds__(PART_BLOCK)
             }
         }
         __syncthreads();
-        for (int j = t; j < ntile; j += PART_BLOCK) {
-            const int p = sp[j];
-            const long long slot = cur[p] + (j - off[p]);
-            lkey[slot] = sk[j];
-            lval[slot] = sv[j];
+        // unrolled: the LDS reads of a thread's rows are in flight together
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int j = t + u * PART_BLOCK;
+            if (j < ntile) {
+                const long long slot = cur[sp[j]] + j;
+                lkey[slot] = sk[j];
+                lval[slot] = sv[j];
+            }
         }
         __syncthreads();
-        for (int i = t; i < F; i += PART_BLOCK) cur[i] += cnt[i];
+        for (int i = t; i < F; i += PART_BLOCK) cur[i] += off[i] + cnt[i];
     }
     report(status, err);
 }
