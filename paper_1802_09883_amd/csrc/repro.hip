@@ -101,8 +101,10 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_sample_lds(const KT* __restrict__
 // inside a partition is not deterministic and needs not be: level sums are
 // exact.
 //
-//   k_part_hist     per-workgroup histogram of partition ids -> counts[w][p]
-//   k_part_offsets  per partition: rows before workgroup w (rel[w][p]), size
+//   k_part_hist     per-tile histogram of partition ids -> counts[t][p]
+//   k_part_round_scan, k_part_round_bases
+//                   per partition: rows before tile t (rel[t][p] within its
+//                   round, roff[k][p] before round k), size
 //   k_part_plan     partition bases, chunking into work items, work table
 //   k_part_scatter  (local key, value) pairs into their partition's range
 //   k_agg_part      one work item = one chunk of one partition, aggregated in
@@ -122,49 +124,110 @@ struct WorkItem {
     long long r0, r1;  // rows in the partitioned arrays
 };
 
+// Tiles of the partition passes.  A tile is the scatter's (RU * PART_BLOCK
+// rows); workgroup w of nw takes tiles w, w + nw, w + 2 nw, ... (round k =
+// t / nw).  Inside a partition the rows are laid out round by round, and in
+// a round workgroup by workgroup in XCD-major order: workgroups are
+// dispatched round-robin over the 8 XCDs (XCD = w mod 8), so the runs that
+// the workgroups of one XCD write into a partition in one round are
+// adjacent and fill whole lines in that XCD's L2, instead of each
+// workgroup's run ending in a partial line that leaves the L2 before the
+// workgroup's next tile completes it.
+constexpr int NXCD = 8;
+
+// Workgroup at position r of the XCD-major order of nw workgroups.
+__host__ __device__ inline int xcd_unrank(int r, int nw) {
+    int x = 0;
+    for (; x < NXCD - 1; ++x) {
+        const int c = (nw - x + NXCD - 1) / NXCD;  // workgroups on XCD x
+        if (r < c) break;
+        r -= c;
+    }
+    return r * NXCD + x;
+}
+
 template <class KT>
 __global__ void __launch_bounds__(PART_BLOCK) k_part_hist(const KT* __restrict__ keys, int64_t n, int64_t G,
-                                                          int gp_shift, int F, int64_t chunk,
+                                                          int gp_shift, int F, int64_t tile,
                                                           int* __restrict__ counts) {
     extern __shared__ __align__(16) unsigned char smem[];
     int* h = reinterpret_cast<int*>(smem);
-    for (int i = threadIdx.x; i < F; i += PART_BLOCK) h[i] = 0;
-    __syncthreads();
-    const int64_t c0 = (int64_t)blockIdx.x * chunk;
-    const int64_t c1 = min(n, c0 + chunk);
+    const int64_t ntiles = (n + tile - 1) / tile;
     constexpr int UH = 8;  // keys in flight per thread
-    for (int64_t b = c0; b < c1; b += (int64_t)UH * PART_BLOCK) {
-        int64_t kk[UH];
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        for (int i = threadIdx.x; i < F; i += PART_BLOCK) h[i] = 0;
+        __syncthreads();
+        const int64_t c0 = t * tile;
+        const int64_t c1 = min(n, c0 + tile);
+        for (int64_t b = c0; b < c1; b += (int64_t)UH * PART_BLOCK) {
+            int64_t kk[UH];
 #pragma unroll
-        for (int u = 0; u < UH; ++u) {
-            const int64_t i = b + u * PART_BLOCK + threadIdx.x;
-            kk[u] = (i < c1) ? (int64_t)__builtin_nontemporal_load(&keys[i]) : -1;
+            for (int u = 0; u < UH; ++u) {
+                const int64_t i = b + u * PART_BLOCK + threadIdx.x;
+                kk[u] = (i < c1) ? (int64_t)__builtin_nontemporal_load(&keys[i]) : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < UH; ++u)
+                if ((uint64_t)kk[u] < (uint64_t)G) atomicAdd(&h[(int)(kk[u] >> gp_shift)], 1);
         }
-#pragma unroll
-        for (int u = 0; u < UH; ++u)
-            if ((uint64_t)kk[u] < (uint64_t)G) atomicAdd(&h[(int)(kk[u] >> gp_shift)], 1);
+        __syncthreads();
+        for (int i = threadIdx.x; i < F; i += PART_BLOCK) counts[t * F + i] = h[i];
+        __syncthreads();  // h is cleared for the next tile
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < F; i += PART_BLOCK) counts[(size_t)blockIdx.x * F + i] = h[i];
 }
 
-// block per partition, one thread per histogram workgroup (blockDim = nw)
-__global__ void __launch_bounds__(PART_WG) k_part_offsets(const int* __restrict__ counts, int nw, int F,
-                                                          int* __restrict__ rel, long long* __restrict__ size) {
-    __shared__ int s[PART_WG];
-    const int p = blockIdx.x, w = threadIdx.x;
-    const int c = (w < nw) ? counts[(size_t)w * F + p] : 0;
-    s[w] = c;
-    __syncthreads();
-    // inclusive scan (Hillis-Steele) over the workgroups
-    for (int o = 1; o < PART_WG; o <<= 1) {
-        const int x = (w >= o) ? s[w - o] : 0;
-        __syncthreads();
-        s[w] += x;
-        __syncthreads();
+// Grid (ceil(F / 64), rounds), 256 threads: 64 partitions x 4 quarters of
+// a round's workgroup positions (at most 64 each, nw <= 256).  Each thread
+// loads its quarter's counts together, then rel[t][p] = rows of p in the
+// round's earlier tiles (XCD-major order) and rsum[k][p] = rows of p in
+// round k.
+constexpr int RS_P = 64;
+__global__ void __launch_bounds__(256) k_part_round_scan(const int* __restrict__ counts, int64_t ntiles, int nw,
+                                                         int F, int* __restrict__ rel, int* __restrict__ rsum) {
+    __shared__ int qsum[4][RS_P];
+    const int pp = threadIdx.x % RS_P, q = threadIdx.x / RS_P;
+    const int p = blockIdx.x * RS_P + pp;
+    const int64_t k = blockIdx.y;
+    const int per = (nw + 3) / 4;
+    const int r0 = min(nw, q * per), r1 = min(nw, r0 + per);
+    int c[RS_P];
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < RS_P; ++j) {
+        c[j] = 0;
+        if (r0 + j < r1 && p < F) {
+            const int64_t t = k * nw + xcd_unrank(r0 + j, nw);
+            if (t < ntiles) c[j] = counts[t * F + p];
+        }
+        s += c[j];
     }
-    if (w < nw) rel[(size_t)w * F + p] = s[w] - c;
-    if (w == PART_WG - 1) size[p] = s[w];
+    qsum[q][pp] = s;
+    __syncthreads();
+    if (p >= F) return;
+    int run = 0;
+    for (int u = 0; u < q; ++u) run += qsum[u][pp];
+#pragma unroll
+    for (int j = 0; j < RS_P; ++j) {
+        if (r0 + j < r1) {
+            const int64_t t = k * nw + xcd_unrank(r0 + j, nw);
+            if (t < ntiles) rel[t * F + p] = run;
+            run += c[j];
+        }
+    }
+    if (q == 3) rsum[k * F + p] = run;
+}
+
+// One thread per partition: roff[k][p] = rows of p before round k; size[p].
+__global__ void __launch_bounds__(256) k_part_round_bases(const int* __restrict__ rsum, int64_t rounds, int F,
+                                                          long long* __restrict__ roff, long long* __restrict__ size) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= F) return;
+    long long run = 0;
+    for (int64_t k = 0; k < rounds; ++k) {
+        roff[k * F + p] = run;
+        run += rsum[k * F + p];
+    }
+    size[p] = run;
 }
 
 // single block: exclusive scans over the partitions (bases, work items).
@@ -285,8 +348,9 @@ __device__ __forceinline__ int block_exclusive_scan(const int* cnt, int* off, in
 template <class KT, class VT, class AT, int RU, bool DOM = true, class LK = uint16_t>
 __global__ void __launch_bounds__(PART_BLOCK)
     k_part_scatter(const KT* __restrict__ keys, const VT* __restrict__ vals, int64_t n, int64_t G, int gp_shift, int F,
-                   int64_t chunk, const long long* __restrict__ base, const int* __restrict__ rel,
-                   LK* __restrict__ lkey, VT* __restrict__ lval, uint32_t* __restrict__ status) {
+                   const long long* __restrict__ base, const long long* __restrict__ roff,
+                   const int* __restrict__ rel, LK* __restrict__ lkey, VT* __restrict__ lval,
+                   uint32_t* __restrict__ status) {
     typedef Fmt<AT> Fm;
     constexpr int SC_TILE = RU * PART_BLOCK;  // RU rows per thread and tile
     extern __shared__ __align__(16) unsigned char smem[];
@@ -298,13 +362,17 @@ __global__ void __launch_bounds__(PART_BLOCK)
     uint16_t* sp = reinterpret_cast<uint16_t*>(sk + SC_TILE);     // staged partitions
     __shared__ int wsum[PART_BLOCK / 64];
     const int t = threadIdx.x;
-    for (int i = t; i < F; i += PART_BLOCK) cur[i] = base[i] + rel[(size_t)blockIdx.x * F + i];
-    const int64_t c0 = (int64_t)blockIdx.x * chunk;
-    const int64_t c1 = min(n, c0 + chunk);
+    const int64_t ntiles = (n + SC_TILE - 1) / SC_TILE;
     const uint32_t gmask = (1u << gp_shift) - 1;
     uint32_t err = 0;
-    for (int64_t tb = c0; tb < c1; tb += SC_TILE) {
-        for (int i = t; i < F; i += PART_BLOCK) cnt[i] = 0;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t tb = tile * SC_TILE;
+        const int64_t c1 = min(n, tb + SC_TILE);
+        const int64_t k = tile / gridDim.x;  // round
+        for (int i = t; i < F; i += PART_BLOCK) {
+            cnt[i] = 0;
+            cur[i] = base[i] + roff[k * F + i] + rel[tile * F + i];
+        }
         __syncthreads();
         int pi[RU], rk[RU];
         int64_t kk[RU];
@@ -368,8 +436,7 @@ __global__ void __launch_bounds__(PART_BLOCK)
                 lval[slot] = sv[j];
             }
         }
-        __syncthreads();
-        for (int i = t; i < F; i += PART_BLOCK) cur[i] += off[i] + cnt[i];
+        __syncthreads();  // the staging area and counts are reused by the next tile
     }
     report(status, err);
 }
@@ -714,7 +781,9 @@ bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
     int64_t nw = (n + (int64_t)PART_BLOCK * 16 - 1) / ((int64_t)PART_BLOCK * 16);
     nw = std::max<int64_t>(1, std::min<int64_t>(PART_WG, nw));
     p->nw = (int)nw;
-    p->chunk_hs = std::max<int64_t>(1, (n + nw - 1) / nw);
+    const int64_t ntiles = (n + (int64_t)p->sc_ru * PART_BLOCK - 1) / ((int64_t)p->sc_ru * PART_BLOCK);
+    const int64_t rounds = std::max<int64_t>(1, (ntiles + nw - 1) / nw);
+    if (rounds > 65535) return false;  // a grid dimension of the round scan
     const int64_t maxw = F + (n + (int64_t)PART_ALIGN * F + PART_CHUNK - 1) / PART_CHUNK;
     if (maxw > INT32_MAX / 2) return false;
     p->maxw = (int)maxw;
@@ -722,8 +791,10 @@ bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
     const int GP = 1 << s;
     size_t ws = 0;
     auto take = [&](size_t bytes) { size_t o = ws; ws += align_up(bytes, 256); return o; };
-    p->o_counts = take((size_t)nw * F * 4);
-    p->o_rel = take((size_t)nw * F * 4);
+    p->o_counts = take((size_t)ntiles * F * 4);
+    p->o_rel = take((size_t)ntiles * F * 4);
+    p->o_rsum = take((size_t)rounds * F * 4);
+    p->o_roff = take((size_t)rounds * F * 8);
     p->o_size = take((size_t)F * 8);
     p->o_base = take((size_t)F * 8);
     p->o_wfirst = take((size_t)F * 4);
@@ -755,11 +826,15 @@ bool make_plan_deep(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
     int64_t nw = (n + (int64_t)PART_BLOCK * 16 - 1) / ((int64_t)PART_BLOCK * 16);
     nw = std::max<int64_t>(1, std::min<int64_t>(PART_WG, nw));
     p->nw = (int)nw;
-    p->chunk_hs = std::max<int64_t>(1, (n + nw - 1) / nw);
+    const int64_t ntiles = (n + (int64_t)p->sc_ru * PART_BLOCK - 1) / ((int64_t)p->sc_ru * PART_BLOCK);
+    const int64_t rounds = std::max<int64_t>(1, (ntiles + nw - 1) / nw);
+    if (rounds > 65535) return false;
     size_t ws = 0;
     auto take = [&](size_t bytes) { size_t o = ws; ws += align_up(bytes, 256); return o; };
-    p->o_counts = take((size_t)nw * F * 4);
-    p->o_rel = take((size_t)nw * F * 4);
+    p->o_counts = take((size_t)ntiles * F * 4);
+    p->o_rel = take((size_t)ntiles * F * 4);
+    p->o_rsum = take((size_t)rounds * F * 4);
+    p->o_roff = take((size_t)rounds * F * 8);
     p->o_size = take((size_t)F * 8);
     p->o_base = take((size_t)F * 8);
     p->o_lkey = take((size_t)n * 4);
@@ -784,6 +859,31 @@ bool make_plan(int64_t n, int64_t G, int L, int jmax, size_t vsize, Plan* p) {
 
 // gbase, Gstride: the call's groups are states' groups gbase .. gbase+G-1 of
 // Gstride (the second partitioning level runs one call per super-partition).
+// The histogram and the per-tile offsets of the partition passes (the
+// scatter's tiles and rounds, see xcd_unrank).
+template <class KT>
+int partition_offsets(const KT* keys, int64_t n, int64_t G, const Plan& p, unsigned char* ws, hipStream_t st) {
+    int* counts = reinterpret_cast<int*>(ws + p.o_counts);
+    int* rel = reinterpret_cast<int*>(ws + p.o_rel);
+    int* rsum = reinterpret_cast<int*>(ws + p.o_rsum);
+    long long* roff = reinterpret_cast<long long*>(ws + p.o_roff);
+    long long* size = reinterpret_cast<long long*>(ws + p.o_size);
+    const int64_t tile = (int64_t)p.sc_ru * PART_BLOCK;
+    const int64_t ntiles = (n + tile - 1) / tile;
+    const int64_t rounds = std::max<int64_t>(1, (ntiles + p.nw - 1) / p.nw);
+    const size_t lds_h = (size_t)p.F * 4;
+    if (!allow_lds((const void*)k_part_hist<KT>, lds_h)) return REPRO_EHIP;
+    hipLaunchKernelGGL(k_part_hist<KT>, dim3(p.nw), dim3(PART_BLOCK), lds_h, st, keys, n, G, p.gp_shift, p.F, tile,
+                       counts);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_part_round_scan, dim3((p.F + RS_P - 1) / RS_P, (unsigned)rounds), dim3(256), 0, st, counts,
+                       ntiles, p.nw, p.F, rel, rsum);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_part_round_bases, dim3((p.F + 255) / 256), dim3(256), 0, st, rsum, rounds, p.F, roff, size);
+    LAUNCH_CHECK();
+    return REPRO_OK;
+}
+
 template <class KT, class VT, class AT, int L>
 int run_groupby_part(const void* keys, const void* values, int64_t n, int64_t G, void* states, void* workspace,
                      uint32_t* status, const Plan& p, hipStream_t st, int64_t gbase = 0, int64_t Gstride = -1) {
@@ -791,8 +891,8 @@ int run_groupby_part(const void* keys, const void* values, int64_t n, int64_t G,
     unsigned char* ws = static_cast<unsigned char*>(workspace);
     const KT* k = static_cast<const KT*>(keys);
     const VT* v = static_cast<const VT*>(values);
-    int* counts = reinterpret_cast<int*>(ws + p.o_counts);
     int* rel = reinterpret_cast<int*>(ws + p.o_rel);
+    long long* roff = reinterpret_cast<long long*>(ws + p.o_roff);
     long long* size = reinterpret_cast<long long*>(ws + p.o_size);
     long long* base = reinterpret_cast<long long*>(ws + p.o_base);
     int* wfirst = reinterpret_cast<int*>(ws + p.o_wfirst);
@@ -805,26 +905,24 @@ int run_groupby_part(const void* keys, const void* values, int64_t n, int64_t G,
     AT* S = static_cast<AT*>(states);
     long long* C = reinterpret_cast<long long*>(static_cast<unsigned char*>(states) +
                                                 align_up((size_t)Gstride * L * sizeof(AT), 8));
-    const size_t lds_h = (size_t)p.F * 4;
     const void* scatter = p.sc_ru == 8 ? (const void*)k_part_scatter<KT, VT, AT, 8> : (const void*)k_part_scatter<KT, VT, AT, 4>;
-    if (!allow_lds((const void*)k_part_hist<KT>, lds_h) || !allow_lds(scatter, p.lds_sc) ||
+    if (!allow_lds(scatter, p.lds_sc) ||
         !allow_lds((const void*)k_agg_part<VT, AT, L>, p.lds_agg2))
         return REPRO_EHIP;
-    hipLaunchKernelGGL(k_part_hist<KT>, dim3(p.nw), dim3(PART_BLOCK), lds_h, st, k, n, G, p.gp_shift, p.F, p.chunk_hs,
-                       counts);
-    LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_part_offsets, dim3(p.F), dim3(PART_WG), 0, st, counts, p.nw, p.F, rel, size);
-    LAUNCH_CHECK();
+    {
+        const int rc = partition_offsets<KT>(k, n, G, p, ws, st);
+        if (rc != REPRO_OK) return rc;
+    }
     hipLaunchKernelGGL(k_part_plan<VT>, dim3(1), dim3(PART_BLOCK), 0, st, size, p.F, PART_CHUNK, base, wfirst, items,
                        nitems, lkey, lval);
     LAUNCH_CHECK();
     prof_before(st);
     if (p.sc_ru == 8)
         hipLaunchKernelGGL((k_part_scatter<KT, VT, AT, 8>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k, v, n, G,
-                           p.gp_shift, p.F, p.chunk_hs, base, rel, lkey, lval, status);
+                           p.gp_shift, p.F, base, roff, rel, lkey, lval, status);
     else
         hipLaunchKernelGGL((k_part_scatter<KT, VT, AT, 4>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k, v, n, G,
-                           p.gp_shift, p.F, p.chunk_hs, base, rel, lkey, lval, status);
+                           p.gp_shift, p.F, base, roff, rel, lkey, lval, status);
     LAUNCH_CHECK();
     prof_after(st);
     prof_before(st);
@@ -860,25 +958,22 @@ int run_groupby_deep(const void* keys, const void* values, int64_t n, int64_t G,
     unsigned char* ws = static_cast<unsigned char*>(workspace);
     const KT* k = static_cast<const KT*>(keys);
     const VT* v = static_cast<const VT*>(values);
-    int* counts = reinterpret_cast<int*>(ws + p.o_counts);
     int* rel = reinterpret_cast<int*>(ws + p.o_rel);
+    long long* roff = reinterpret_cast<long long*>(ws + p.o_roff);
     long long* size = reinterpret_cast<long long*>(ws + p.o_size);
     long long* base = reinterpret_cast<long long*>(ws + p.o_base);
     uint32_t* lkey = reinterpret_cast<uint32_t*>(ws + p.o_lkey);
     VT* lval = reinterpret_cast<VT*>(ws + p.o_lval);
-    const size_t lds_h = (size_t)p.F * 4;
-    if (!allow_lds((const void*)k_part_hist<KT>, lds_h) ||
-        !allow_lds((const void*)k_part_scatter<KT, VT, AT, 8, true, uint32_t>, p.lds_sc))
+    if (!allow_lds((const void*)k_part_scatter<KT, VT, AT, 8, true, uint32_t>, p.lds_sc))
         return REPRO_EHIP;
-    hipLaunchKernelGGL(k_part_hist<KT>, dim3(p.nw), dim3(PART_BLOCK), lds_h, st, k, n, G, p.gp_shift, p.F, p.chunk_hs,
-                       counts);
-    LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_part_offsets, dim3(p.F), dim3(PART_WG), 0, st, counts, p.nw, p.F, rel, size);
-    LAUNCH_CHECK();
+    {
+        const int rc = partition_offsets<KT>(k, n, G, p, ws, st);
+        if (rc != REPRO_OK) return rc;
+    }
     hipLaunchKernelGGL(k_part_bases, dim3(1), dim3(64), 0, st, size, p.F, base);
     LAUNCH_CHECK();
     hipLaunchKernelGGL((k_part_scatter<KT, VT, AT, 8, true, uint32_t>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k,
-                       v, n, G, p.gp_shift, p.F, p.chunk_hs, base, rel, lkey, lval, status);
+                       v, n, G, p.gp_shift, p.F, base, roff, rel, lkey, lval, status);
     LAUNCH_CHECK();
     long long hsize[DEEP_MAX_F];
     if (hipMemcpyAsync(hsize, size, (size_t)p.F * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -1030,8 +1125,8 @@ int run_plain_part(const void* keys, const void* values, int64_t n, int64_t G, d
     unsigned char* ws = static_cast<unsigned char*>(workspace);
     const KT* k = static_cast<const KT*>(keys);
     const VT* v = static_cast<const VT*>(values);
-    int* counts = reinterpret_cast<int*>(ws + p.o_counts);
     int* rel = reinterpret_cast<int*>(ws + p.o_rel);
+    long long* roff = reinterpret_cast<long long*>(ws + p.o_roff);
     long long* size = reinterpret_cast<long long*>(ws + p.o_size);
     long long* base = reinterpret_cast<long long*>(ws + p.o_base);
     int* wfirst = reinterpret_cast<int*>(ws + p.o_wfirst);
@@ -1039,26 +1134,24 @@ int run_plain_part(const void* keys, const void* values, int64_t n, int64_t G, d
     int* nitems = reinterpret_cast<int*>(ws + p.o_nitems);
     uint16_t* lkey = reinterpret_cast<uint16_t*>(ws + p.o_lkey);
     VT* lval = reinterpret_cast<VT*>(ws + p.o_lval);
-    const size_t lds_h = (size_t)p.F * 4;
     const void* scatter = p.sc_ru == 8 ? (const void*)k_part_scatter<KT, VT, double, 8, false>
                                        : (const void*)k_part_scatter<KT, VT, double, 4, false>;
-    if (!allow_lds((const void*)k_part_hist<KT>, lds_h) || !allow_lds(scatter, p.lds_sc) ||
+    if (!allow_lds(scatter, p.lds_sc) ||
         !allow_lds((const void*)k_agg_part_plain<VT>, p.lds_agg2))
         return REPRO_EHIP;
-    hipLaunchKernelGGL(k_part_hist<KT>, dim3(p.nw), dim3(PART_BLOCK), lds_h, st, k, n, G, p.gp_shift, p.F, p.chunk_hs,
-                       counts);
-    LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_part_offsets, dim3(p.F), dim3(PART_WG), 0, st, counts, p.nw, p.F, rel, size);
-    LAUNCH_CHECK();
+    {
+        const int rc = partition_offsets<KT>(k, n, G, p, ws, st);
+        if (rc != REPRO_OK) return rc;
+    }
     hipLaunchKernelGGL(k_part_plan<VT>, dim3(1), dim3(PART_BLOCK), 0, st, size, p.F, PART_CHUNK, base, wfirst, items,
                        nitems, lkey, lval);
     LAUNCH_CHECK();
     if (p.sc_ru == 8)
         hipLaunchKernelGGL((k_part_scatter<KT, VT, double, 8, false>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k, v,
-                           n, G, p.gp_shift, p.F, p.chunk_hs, base, rel, lkey, lval, status);
+                           n, G, p.gp_shift, p.F, base, roff, rel, lkey, lval, status);
     else
         hipLaunchKernelGGL((k_part_scatter<KT, VT, double, 4, false>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k, v,
-                           n, G, p.gp_shift, p.F, p.chunk_hs, base, rel, lkey, lval, status);
+                           n, G, p.gp_shift, p.F, base, roff, rel, lkey, lval, status);
     LAUNCH_CHECK();
     hipLaunchKernelGGL((k_agg_part_plain<VT>), dim3(p.maxw), dim3(PLAIN_PART_BLOCK), p.lds_agg2, st, lkey, lval, items,
                        nitems, G, p.gp_shift, out);

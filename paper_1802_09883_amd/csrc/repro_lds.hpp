@@ -230,9 +230,9 @@ struct Plan {
     int gp_shift, F, nw;     // groups per partition 2^gp_shift, partitions, hist/scatter workgroups
     size_t lds_sc;           // scatter LDS
     int sc_ru;               // scatter rows per thread and tile
-    int64_t chunk_hs;        // rows per hist/scatter workgroup
     int maxw;                // work items, upper bound
     size_t o_counts, o_rel, o_size, o_base, o_wfirst, o_items, o_nitems, o_lkey, o_lval, o_ptop, o_pK;
+    size_t o_rsum, o_roff;   // per-round partition counts and offsets
     size_t lds_agg2;         // LDS of k_agg_part
     size_t o_l2, ws_l2;      // path 3: the one-level workspace of a super-partition, and its size
     int nwg;        // aggregate workgroups
