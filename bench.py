@@ -760,7 +760,8 @@ def cpu_baseline(keys, cols, G, L, seconds, T64=True):
     # beside it, on a prefix of about a second's work: the oracle on one
     # thread, and a plain (non-reproducible) FP64 GroupBy-SUM on one thread
     # (numpy bincount with weights), both over every column
-    m1 = int(min(len(keys), max(10 ** 5, rate / max(cores, 1))))
+    # (at least 1e6 rows: each oracle call also initialises every group's state)
+    m1 = int(min(len(keys), max(10 ** 6, rate / max(cores, 1))))
     t0 = time.perf_counter()
     for v in cols:
         st, _ = oracle.groupby_sum(keys[:m1], v[:m1], G, L, T64, threads=1)
