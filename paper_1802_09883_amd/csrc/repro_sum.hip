@@ -27,7 +27,7 @@ namespace {
 constexpr int SUM_BLOCK = 256;     // 4 waves
 constexpr int SUM_RPT = 8;         // rows per lane and step
 constexpr int SUM_STEP = SUM_BLOCK * SUM_RPT;
-constexpr int SUM_MAX_WG = 2048;   // 8 workgroups per CU
+constexpr int SUM_MAX_WG = 1024;   // 4 workgroups per CU: half the partials of 8 for the merge, same bandwidth
 constexpr int64_t SUM_MAX_ROWS_PER_LANE = 1 << 16;  // lane sums stay below 2^55
 
 // Level words of a lane moved down by d levels (the lowest fall off).
