@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(256) k_zero(unsigned long long* __restrict__ p
 // caller's state the same way and writes the canonical (S, C).
 constexpr int M1_GROUPS = 64, M1_WAVES = 4;
 constexpr int M2_GROUPS = 16, M2_SLICES = 16;
-constexpr int64_t MERGE_DIRECT_MAX = 1 << 16;  // partials x groups merged by k_merge_l2 alone
+constexpr int64_t MERGE_DIRECT_MAX = 1 << 20;  // partials x groups merged by k_merge_l2 alone (one launch)
 constexpr int SEED_TILES = 64;      // tiles sampled for seed tops
 constexpr int SEED_MIN_TILES = 8;   // tiles per workgroup from which sampling pays
 

@@ -124,11 +124,11 @@ def test_largest_lds_group_count(L, extra):
     check_case(keys, vals, G, L, True, "largest LDS G" if extra == 0 else "one group beyond LDS")
 
 
-@pytest.mark.parametrize("G,tiles", [(1024, 64), (1024, 65), (1025, 8), (16, 256)])
+@pytest.mark.parametrize("G,tiles", [(4096, 256), (4097, 256), (1024, 65), (1025, 8), (16, 256)])
 def test_merge_launch_limits(G, tiles):
-    """Few partials (partials x groups <= 2^16) are merged by one launch,
-    more by two; around that limit, and resumed from a state whose tops are
-    above the new rows'."""
+    """Few partials (partials x groups <= 2^20: one workgroup per tile here)
+    are merged by one launch, more by two; around that limit, and resumed
+    from a state whose tops are above the new rows'."""
     rng = np.random.default_rng([G, tiles])
     n = tiles * 8192
     keys = rng.integers(0, G, n).astype(np.int32)
