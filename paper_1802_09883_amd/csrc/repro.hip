@@ -101,9 +101,9 @@ __global__ void __launch_bounds__(AGG_BLOCK) k_sample_lds(const KT* __restrict__
 // inside a partition is not deterministic and needs not be: level sums are
 // exact.
 //
-//   k_part_hist     per-tile histogram of partition ids -> counts[t][p]
+//   k_part_hist     per-slab histogram of partition ids -> counts[s][p]
 //   k_part_round_scan, k_part_round_bases
-//                   per partition: rows before tile t (rel[t][p] within its
+//                   per partition: rows before slab s (rel[s][p] within its
 //                   round, roff[k][p] before round k), size
 //   k_part_plan     partition bases, chunking into work items, work table
 //   k_part_scatter  (local key, value) pairs into their partition's range
@@ -124,15 +124,16 @@ struct WorkItem {
     long long r0, r1;  // rows in the partitioned arrays
 };
 
-// Tiles of the partition passes.  A tile is the scatter's (RU * PART_BLOCK
-// rows); workgroup w of nw takes tiles w, w + nw, w + 2 nw, ... (round k =
-// t / nw).  Inside a partition the rows are laid out round by round, and in
-// a round workgroup by workgroup in XCD-major order: workgroups are
-// dispatched round-robin over the 8 XCDs (XCD = w mod 8), so the runs that
-// the workgroups of one XCD write into a partition in one round are
-// adjacent and fill whole lines in that XCD's L2, instead of each
-// workgroup's run ending in a partial line that leaves the L2 before the
-// workgroup's next tile completes it.
+// Slabs of the partition passes.  A slab is one or more of the scatter's
+// tiles (RU * PART_BLOCK rows; several when the partitions are so many that
+// per-tile counts would cost more than a byte per row); workgroup w of nw
+// takes slabs w, w + nw, w + 2 nw, ... (round k = s / nw).  Inside a
+// partition the rows are laid out round by round, and in a round workgroup
+// by workgroup in XCD-major order: workgroups are dispatched round-robin
+// over the 8 XCDs (XCD = w mod 8), so the runs that the workgroups of one
+// XCD write into a partition in one round are adjacent and fill whole lines
+// in that XCD's L2, instead of each workgroup's run ending in a partial line
+// that leaves the L2 before the workgroup's next slab completes it.
 constexpr int NXCD = 8;
 
 // Workgroup at position r of the XCD-major order of nw workgroups.
@@ -148,17 +149,17 @@ __host__ __device__ inline int xcd_unrank(int r, int nw) {
 
 template <class KT>
 __global__ void __launch_bounds__(PART_BLOCK) k_part_hist(const KT* __restrict__ keys, int64_t n, int64_t G,
-                                                          int gp_shift, int F, int64_t tile,
+                                                          int gp_shift, int F, int64_t slab,
                                                           int* __restrict__ counts) {
     extern __shared__ __align__(16) unsigned char smem[];
     int* h = reinterpret_cast<int*>(smem);
-    const int64_t ntiles = (n + tile - 1) / tile;
+    const int64_t nslabs = (n + slab - 1) / slab;
     constexpr int UH = 8;  // keys in flight per thread
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (int64_t t = blockIdx.x; t < nslabs; t += gridDim.x) {
         for (int i = threadIdx.x; i < F; i += PART_BLOCK) h[i] = 0;
         __syncthreads();
-        const int64_t c0 = t * tile;
-        const int64_t c1 = min(n, c0 + tile);
+        const int64_t c0 = t * slab;
+        const int64_t c1 = min(n, c0 + slab);
         for (int64_t b = c0; b < c1; b += (int64_t)UH * PART_BLOCK) {
             int64_t kk[UH];
 #pragma unroll
@@ -172,17 +173,17 @@ __global__ void __launch_bounds__(PART_BLOCK) k_part_hist(const KT* __restrict__
         }
         __syncthreads();
         for (int i = threadIdx.x; i < F; i += PART_BLOCK) counts[t * F + i] = h[i];
-        __syncthreads();  // h is cleared for the next tile
+        __syncthreads();  // h is cleared for the next slab
     }
 }
 
 // Grid (ceil(F / 64), rounds), 256 threads: 64 partitions x 4 quarters of
 // a round's workgroup positions (at most 64 each, nw <= 256).  Each thread
-// loads its quarter's counts together, then rel[t][p] = rows of p in the
-// round's earlier tiles (XCD-major order) and rsum[k][p] = rows of p in
+// loads its quarter's counts together, then rel[s][p] = rows of p in the
+// round's earlier slabs (XCD-major order) and rsum[k][p] = rows of p in
 // round k.
 constexpr int RS_P = 64;
-__global__ void __launch_bounds__(256) k_part_round_scan(const int* __restrict__ counts, int64_t ntiles, int nw,
+__global__ void __launch_bounds__(256) k_part_round_scan(const int* __restrict__ counts, int64_t nslabs, int nw,
                                                          int F, int* __restrict__ rel, int* __restrict__ rsum) {
     __shared__ int qsum[4][RS_P];
     const int pp = threadIdx.x % RS_P, q = threadIdx.x / RS_P;
@@ -197,7 +198,7 @@ __global__ void __launch_bounds__(256) k_part_round_scan(const int* __restrict__
         c[j] = 0;
         if (r0 + j < r1 && p < F) {
             const int64_t t = k * nw + xcd_unrank(r0 + j, nw);
-            if (t < ntiles) c[j] = counts[t * F + p];
+            if (t < nslabs) c[j] = counts[t * F + p];
         }
         s += c[j];
     }
@@ -210,7 +211,7 @@ __global__ void __launch_bounds__(256) k_part_round_scan(const int* __restrict__
     for (int j = 0; j < RS_P; ++j) {
         if (r0 + j < r1) {
             const int64_t t = k * nw + xcd_unrank(r0 + j, nw);
-            if (t < ntiles) rel[t * F + p] = run;
+            if (t < nslabs) rel[t * F + p] = run;
             run += c[j];
         }
     }
@@ -348,7 +349,7 @@ __device__ __forceinline__ int block_exclusive_scan(const int* cnt, int* off, in
 template <class KT, class VT, class AT, int RU, bool DOM = true, class LK = uint16_t>
 __global__ void __launch_bounds__(PART_BLOCK)
     k_part_scatter(const KT* __restrict__ keys, const VT* __restrict__ vals, int64_t n, int64_t G, int gp_shift, int F,
-                   const long long* __restrict__ base, const long long* __restrict__ roff,
+                   int64_t slab, const long long* __restrict__ base, const long long* __restrict__ roff,
                    const int* __restrict__ rel, LK* __restrict__ lkey, VT* __restrict__ lval,
                    uint32_t* __restrict__ status) {
     typedef Fmt<AT> Fm;
@@ -362,81 +363,85 @@ __global__ void __launch_bounds__(PART_BLOCK)
     uint16_t* sp = reinterpret_cast<uint16_t*>(sk + SC_TILE);     // staged partitions
     __shared__ int wsum[PART_BLOCK / 64];
     const int t = threadIdx.x;
-    const int64_t ntiles = (n + SC_TILE - 1) / SC_TILE;
+    const int64_t nslabs = (n + slab - 1) / slab;
     const uint32_t gmask = (1u << gp_shift) - 1;
     uint32_t err = 0;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t tb = tile * SC_TILE;
-        const int64_t c1 = min(n, tb + SC_TILE);
-        const int64_t k = tile / gridDim.x;  // round
-        for (int i = t; i < F; i += PART_BLOCK) {
-            cnt[i] = 0;
-            cur[i] = base[i] + roff[k * F + i] + rel[tile * F + i];
-        }
-        __syncthreads();
-        int pi[RU], rk[RU];
-        int64_t kk[RU];
-        LK lk[RU];
-        VT vv[RU];
-        // loads first, so that the memory requests of all rows overlap
+    for (int64_t sl = blockIdx.x; sl < nslabs; sl += gridDim.x) {
+        const int64_t k = sl / gridDim.x;  // round
+        const int64_t s1 = min(n, (sl + 1) * slab);
+        for (int64_t tb = sl * slab; tb < s1; tb += SC_TILE) {
+            const int64_t c1 = min(s1, tb + SC_TILE);
+            for (int i = t; i < F; i += PART_BLOCK) {
+                cnt[i] = 0;
+                if (tb == sl * slab) cur[i] = base[i] + roff[k * F + i] + rel[sl * F + i];  // the slab's first slots
+            }
+            __syncthreads();
+            int pi[RU], rk[RU];
+            int64_t kk[RU];
+            LK lk[RU];
+            VT vv[RU];
+            // loads first, so that the memory requests of all rows overlap
 #pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int64_t i = tb + u * PART_BLOCK + t;
-            kk[u] = (i < c1) ? (int64_t)__builtin_nontemporal_load(&keys[i]) : -1;
-            vv[u] = (i < c1) ? __builtin_nontemporal_load(&vals[i]) : (VT)0;
-        }
+            for (int u = 0; u < RU; ++u) {
+                const int64_t i = tb + u * PART_BLOCK + t;
+                kk[u] = (i < c1) ? (int64_t)__builtin_nontemporal_load(&keys[i]) : -1;
+                vv[u] = (i < c1) ? __builtin_nontemporal_load(&vals[i]) : (VT)0;
+            }
 #pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int64_t i = tb + u * PART_BLOCK + t;
-            pi[u] = -1;
-            if (i < c1) {
-                const int64_t key = kk[u];
-                VT v = vv[u];
-                // every row's value is classified, whatever its key, so the
-                // status bits are those of the LDS path
-                if (!finite_val(v)) {
-                    err |= ERR_NONFINITE;
-                    v = (VT)0;
-                } else if (DOM && v != (VT)0 && jreq_raw<AT>(frexp_raw(v)) > Fm::JMAX) {
-                    err |= ERR_RANGE;
-                    v = (VT)0;
+            for (int u = 0; u < RU; ++u) {
+                const int64_t i = tb + u * PART_BLOCK + t;
+                pi[u] = -1;
+                if (i < c1) {
+                    const int64_t key = kk[u];
+                    VT v = vv[u];
+                    // every row's value is classified, whatever its key, so the
+                    // status bits are those of the LDS path
+                    if (!finite_val(v)) {
+                        err |= ERR_NONFINITE;
+                        v = (VT)0;
+                    } else if (DOM && v != (VT)0 && jreq_raw<AT>(frexp_raw(v)) > Fm::JMAX) {
+                        err |= ERR_RANGE;
+                        v = (VT)0;
+                    }
+                    if ((uint64_t)key < (uint64_t)G) {
+                        pi[u] = (int)(key >> gp_shift);
+                        lk[u] = (LK)((uint32_t)key & gmask);
+                        vv[u] = v;
+                        rk[u] = atomicAdd(&cnt[pi[u]], 1);
+                    } else {
+                        err |= ERR_KEY;
+                    }
                 }
-                if ((uint64_t)key < (uint64_t)G) {
-                    pi[u] = (int)(key >> gp_shift);
-                    lk[u] = (LK)((uint32_t)key & gmask);
-                    vv[u] = v;
-                    rk[u] = atomicAdd(&cnt[pi[u]], 1);
-                } else {
-                    err |= ERR_KEY;
+            }
+            __syncthreads();  // all tile counts in place
+            // off: the partitions' offsets in the tile; cur[p] becomes the slot of
+            // the tile's first row of p minus off[p], so a staged row j of p goes
+            // to slot cur[p] + j (one LDS read fewer per row when writing out)
+            const int ntile = block_exclusive_scan(cnt, off, F, wsum, cur);
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                if (pi[u] >= 0) {
+                    const int pos = off[pi[u]] + rk[u];
+                    sv[pos] = vv[u];
+                    sk[pos] = lk[u];
+                    sp[pos] = (uint16_t)pi[u];
                 }
             }
-        }
-        __syncthreads();  // all tile counts in place
-        // off: the partitions' offsets in the tile; cur[p] becomes the slot of
-        // the tile's first row of p minus off[p], so a staged row j of p goes
-        // to slot cur[p] + j (one LDS read fewer per row when writing out)
-        const int ntile = block_exclusive_scan(cnt, off, F, wsum, cur);
+            __syncthreads();
+            // unrolled: the LDS reads of a thread's rows are in flight together
 #pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            if (pi[u] >= 0) {
-                const int pos = off[pi[u]] + rk[u];
-                sv[pos] = vv[u];
-                sk[pos] = lk[u];
-                sp[pos] = (uint16_t)pi[u];
+            for (int u = 0; u < RU; ++u) {
+                const int j = t + u * PART_BLOCK;
+                if (j < ntile) {
+                    const long long slot = cur[sp[j]] + j;
+                    lkey[slot] = sk[j];
+                    lval[slot] = sv[j];
+                }
             }
+            __syncthreads();  // the staging area and counts are reused by the next tile
+            if (tb + SC_TILE < s1)  // the slab's next tile follows its slots
+                for (int i = t; i < F; i += PART_BLOCK) cur[i] += off[i] + cnt[i];
         }
-        __syncthreads();
-        // unrolled: the LDS reads of a thread's rows are in flight together
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int j = t + u * PART_BLOCK;
-            if (j < ntile) {
-                const long long slot = cur[sp[j]] + j;
-                lkey[slot] = sk[j];
-                lval[slot] = sv[j];
-            }
-        }
-        __syncthreads();  // the staging area and counts are reused by the next tile
     }
     report(status, err);
 }
@@ -767,6 +772,15 @@ bool valid_common(int64_t G, repro_scalar_t T, int L) {
 // partition holds 2^s groups, the largest power of two up to 2^smax whose
 // `gbytes` LDS bytes per group (plus one slot) fit the budget.  The plain
 // baseline (L = 0) keeps one double per group and no partials.
+// Rows of a slab of the partition passes: whole scatter tiles, enough of
+// them that the per-slab counts and offsets (8 bytes per partition) stay
+// within about a byte per row.
+inline int64_t part_slab_rows(int sc_ru, int64_t F) {
+    const int64_t tile = (int64_t)sc_ru * PART_BLOCK;
+    const int64_t tiles = std::max<int64_t>(1, (8 * F + tile - 1) / tile);
+    return tiles * tile;
+}
+
 bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
     p->path = 2;
     const size_t gbytes = L > 0 ? (size_t)8 * L + 12 : 8;
@@ -781,8 +795,9 @@ bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
     int64_t nw = (n + (int64_t)PART_BLOCK * 16 - 1) / ((int64_t)PART_BLOCK * 16);
     nw = std::max<int64_t>(1, std::min<int64_t>(PART_WG, nw));
     p->nw = (int)nw;
-    const int64_t ntiles = (n + (int64_t)p->sc_ru * PART_BLOCK - 1) / ((int64_t)p->sc_ru * PART_BLOCK);
-    const int64_t rounds = std::max<int64_t>(1, (ntiles + nw - 1) / nw);
+    p->slab = part_slab_rows(p->sc_ru, F);
+    const int64_t nslabs = (n + p->slab - 1) / p->slab;
+    const int64_t rounds = std::max<int64_t>(1, (nslabs + nw - 1) / nw);
     if (rounds > 65535) return false;  // a grid dimension of the round scan
     const int64_t maxw = F + (n + (int64_t)PART_ALIGN * F + PART_CHUNK - 1) / PART_CHUNK;
     if (maxw > INT32_MAX / 2) return false;
@@ -791,8 +806,8 @@ bool make_plan_part(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
     const int GP = 1 << s;
     size_t ws = 0;
     auto take = [&](size_t bytes) { size_t o = ws; ws += align_up(bytes, 256); return o; };
-    p->o_counts = take((size_t)ntiles * F * 4);
-    p->o_rel = take((size_t)ntiles * F * 4);
+    p->o_counts = take((size_t)nslabs * F * 4);
+    p->o_rel = take((size_t)nslabs * F * 4);
     p->o_rsum = take((size_t)rounds * F * 4);
     p->o_roff = take((size_t)rounds * F * 8);
     p->o_size = take((size_t)F * 8);
@@ -826,13 +841,14 @@ bool make_plan_deep(int64_t n, int64_t G, int L, size_t vsize, Plan* p) {
     int64_t nw = (n + (int64_t)PART_BLOCK * 16 - 1) / ((int64_t)PART_BLOCK * 16);
     nw = std::max<int64_t>(1, std::min<int64_t>(PART_WG, nw));
     p->nw = (int)nw;
-    const int64_t ntiles = (n + (int64_t)p->sc_ru * PART_BLOCK - 1) / ((int64_t)p->sc_ru * PART_BLOCK);
-    const int64_t rounds = std::max<int64_t>(1, (ntiles + nw - 1) / nw);
+    p->slab = part_slab_rows(p->sc_ru, F);
+    const int64_t nslabs = (n + p->slab - 1) / p->slab;
+    const int64_t rounds = std::max<int64_t>(1, (nslabs + nw - 1) / nw);
     if (rounds > 65535) return false;
     size_t ws = 0;
     auto take = [&](size_t bytes) { size_t o = ws; ws += align_up(bytes, 256); return o; };
-    p->o_counts = take((size_t)ntiles * F * 4);
-    p->o_rel = take((size_t)ntiles * F * 4);
+    p->o_counts = take((size_t)nslabs * F * 4);
+    p->o_rel = take((size_t)nslabs * F * 4);
     p->o_rsum = take((size_t)rounds * F * 4);
     p->o_roff = take((size_t)rounds * F * 8);
     p->o_size = take((size_t)F * 8);
@@ -859,8 +875,8 @@ bool make_plan(int64_t n, int64_t G, int L, int jmax, size_t vsize, Plan* p) {
 
 // gbase, Gstride: the call's groups are states' groups gbase .. gbase+G-1 of
 // Gstride (the second partitioning level runs one call per super-partition).
-// The histogram and the per-tile offsets of the partition passes (the
-// scatter's tiles and rounds, see xcd_unrank).
+// The histogram and the per-slab offsets of the partition passes (the
+// scatter's slabs and rounds, see xcd_unrank).
 template <class KT>
 int partition_offsets(const KT* keys, int64_t n, int64_t G, const Plan& p, unsigned char* ws, hipStream_t st) {
     int* counts = reinterpret_cast<int*>(ws + p.o_counts);
@@ -868,16 +884,15 @@ int partition_offsets(const KT* keys, int64_t n, int64_t G, const Plan& p, unsig
     int* rsum = reinterpret_cast<int*>(ws + p.o_rsum);
     long long* roff = reinterpret_cast<long long*>(ws + p.o_roff);
     long long* size = reinterpret_cast<long long*>(ws + p.o_size);
-    const int64_t tile = (int64_t)p.sc_ru * PART_BLOCK;
-    const int64_t ntiles = (n + tile - 1) / tile;
-    const int64_t rounds = std::max<int64_t>(1, (ntiles + p.nw - 1) / p.nw);
+    const int64_t nslabs = (n + p.slab - 1) / p.slab;
+    const int64_t rounds = std::max<int64_t>(1, (nslabs + p.nw - 1) / p.nw);
     const size_t lds_h = (size_t)p.F * 4;
     if (!allow_lds((const void*)k_part_hist<KT>, lds_h)) return REPRO_EHIP;
-    hipLaunchKernelGGL(k_part_hist<KT>, dim3(p.nw), dim3(PART_BLOCK), lds_h, st, keys, n, G, p.gp_shift, p.F, tile,
+    hipLaunchKernelGGL(k_part_hist<KT>, dim3(p.nw), dim3(PART_BLOCK), lds_h, st, keys, n, G, p.gp_shift, p.F, p.slab,
                        counts);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_part_round_scan, dim3((p.F + RS_P - 1) / RS_P, (unsigned)rounds), dim3(256), 0, st, counts,
-                       ntiles, p.nw, p.F, rel, rsum);
+                       nslabs, p.nw, p.F, rel, rsum);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_part_round_bases, dim3((p.F + 255) / 256), dim3(256), 0, st, rsum, rounds, p.F, roff, size);
     LAUNCH_CHECK();
@@ -919,10 +934,10 @@ int run_groupby_part(const void* keys, const void* values, int64_t n, int64_t G,
     prof_before(st);
     if (p.sc_ru == 8)
         hipLaunchKernelGGL((k_part_scatter<KT, VT, AT, 8>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k, v, n, G,
-                           p.gp_shift, p.F, base, roff, rel, lkey, lval, status);
+                           p.gp_shift, p.F, p.slab, base, roff, rel, lkey, lval, status);
     else
         hipLaunchKernelGGL((k_part_scatter<KT, VT, AT, 4>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k, v, n, G,
-                           p.gp_shift, p.F, base, roff, rel, lkey, lval, status);
+                           p.gp_shift, p.F, p.slab, base, roff, rel, lkey, lval, status);
     LAUNCH_CHECK();
     prof_after(st);
     prof_before(st);
@@ -973,7 +988,7 @@ int run_groupby_deep(const void* keys, const void* values, int64_t n, int64_t G,
     hipLaunchKernelGGL(k_part_bases, dim3(1), dim3(64), 0, st, size, p.F, base);
     LAUNCH_CHECK();
     hipLaunchKernelGGL((k_part_scatter<KT, VT, AT, 8, true, uint32_t>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k,
-                       v, n, G, p.gp_shift, p.F, base, roff, rel, lkey, lval, status);
+                       v, n, G, p.gp_shift, p.F, p.slab, base, roff, rel, lkey, lval, status);
     LAUNCH_CHECK();
     long long hsize[DEEP_MAX_F];
     if (hipMemcpyAsync(hsize, size, (size_t)p.F * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -1148,10 +1163,10 @@ int run_plain_part(const void* keys, const void* values, int64_t n, int64_t G, d
     LAUNCH_CHECK();
     if (p.sc_ru == 8)
         hipLaunchKernelGGL((k_part_scatter<KT, VT, double, 8, false>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k, v,
-                           n, G, p.gp_shift, p.F, base, roff, rel, lkey, lval, status);
+                           n, G, p.gp_shift, p.F, p.slab, base, roff, rel, lkey, lval, status);
     else
         hipLaunchKernelGGL((k_part_scatter<KT, VT, double, 4, false>), dim3(p.nw), dim3(PART_BLOCK), p.lds_sc, st, k, v,
-                           n, G, p.gp_shift, p.F, base, roff, rel, lkey, lval, status);
+                           n, G, p.gp_shift, p.F, p.slab, base, roff, rel, lkey, lval, status);
     LAUNCH_CHECK();
     hipLaunchKernelGGL((k_agg_part_plain<VT>), dim3(p.maxw), dim3(PLAIN_PART_BLOCK), p.lds_agg2, st, lkey, lval, items,
                        nitems, G, p.gp_shift, out);

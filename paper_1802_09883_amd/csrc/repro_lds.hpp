@@ -233,6 +233,7 @@ struct Plan {
     int maxw;                // work items, upper bound
     size_t o_counts, o_rel, o_size, o_base, o_wfirst, o_items, o_nitems, o_lkey, o_lval, o_ptop, o_pK;
     size_t o_rsum, o_roff;   // per-round partition counts and offsets
+    int64_t slab;            // rows per slab of the partition passes
     size_t lds_agg2;         // LDS of k_agg_part
     size_t o_l2, ws_l2;      // path 3: the one-level workspace of a super-partition, and its size
     int nwg;        // aggregate workgroups
