@@ -224,6 +224,8 @@ __global__ void __launch_bounds__(256) k_part_round_bases(const int* __restrict_
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= F) return;
     long long run = 0;
+    // unrolled: the loads of several rounds in flight at once
+#pragma unroll 8
     for (int64_t k = 0; k < rounds; ++k) {
         roff[k * F + p] = run;
         run += rsum[k * F + p];
