@@ -454,6 +454,20 @@ def test_two_partitioning_levels(L, G):
     assert_same_states(st, orc, G, L, True, "two levels, resumed")
 
 
+def test_partitioned_multi_tile_slabs_over_several_rounds():
+    """About 2000 partitions: the partition passes take slabs of two tiles,
+    and with 10M rows the scatter workgroups go through several rounds, so
+    rows land by (round, XCD-major workgroup order) with multi-tile runs.
+    Bad keys and NaN rows on the way."""
+    rng = np.random.default_rng(57)
+    G, n = 8_000_000, 10_000_000
+    keys = rng.integers(-2, G + 2, n).astype(np.int64)
+    vals = np.ldexp(rng.standard_normal(n), rng.integers(-100, 100, n))
+    vals[rng.random(n) < 1e-5] = np.nan
+    say(f"case multi-tile slabs: n={n}, G={G}, L=2")
+    check_case(keys, vals, G, 2, True, "multi-tile slabs, several rounds")
+
+
 def test_partitioned_many_partitions_small_tiles():
     """Thousands of partitions (the scatter falls back to 4096-row tiles)."""
     rng = np.random.default_rng(55)
