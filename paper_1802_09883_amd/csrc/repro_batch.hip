@@ -626,7 +626,9 @@ bool make_batch_plan(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
             for (int c = 0; c < b.nchunks; ++c) {
                 hp->items.push_back(BatchItem{j, c, -1, 0});
                 // two passes over the chunk, then its slices' rows once more
-                cost.push_back(3 * std::min<int64_t>(chunk, u.n - (int64_t)c * chunk));
+                // and a partial per slice: measured at about 5-6 times the
+                // time per row of an unsliced item (the weight orders the queue)
+                cost.push_back(6 * std::min<int64_t>(chunk, u.n - (int64_t)c * chunk));
             }
             continue;
         }
