@@ -147,6 +147,27 @@ def test_batch_workspace_and_validation_without_gpu(lib):
                                    ctypes.byref(plan), None) == _lib.REPRO_EINVAL
 
 
+def test_batch_split_modes_without_gpu(lib):
+    """Jobs beyond one workgroup's LDS: sorting their chunks (split 0, the
+    default) needs a scratch copy of the rows in the workspace, re-reading
+    them per slice (split 1) does not; past 64 slices a job falls back to
+    re-reading, so the two modes then need the same workspace."""
+    def need(specs, split, cap=0):
+        cfg = _lib.BatchConfig(1 << 19, cap, 0, 0, split)
+        return lib.repro_batch_workspace_bytes(_jobs(specs), len(specs), _lib.I32, _lib.F64, _lib.F64,
+                                               ctypes.byref(cfg))
+    big = [(5_000_000, 60_000, 2)]
+    sorted_ws, reread_ws = need(big, 0), need(big, 1)
+    assert sorted_ws > 0 and reread_ws > 0
+    assert sorted_ws - reread_ws >= 5_000_000 * (2 + 8)  # 16-bit local keys and the values
+    small = [(5_000_000, 4000, 2)]  # fits one workgroup's LDS: no slices, no copy
+    assert need(small, 0) == need(small, 1)
+    many = [(5_000_000, 60_000, 2)]  # slices of at most 256 groups: more than 64 of them
+    assert need(many, 0, cap=256) == need(many, 1, cap=256)
+    bad = _lib.BatchConfig(1 << 19, 0, 0, 0, 2)
+    assert lib.repro_batch_workspace_bytes(_jobs(big), 1, _lib.I32, _lib.F64, _lib.F64, ctypes.byref(bad)) == 0
+
+
 def test_query_bytes_without_gpu(lib):
     q = _lib.Query()
     q.keys = 0x1000
