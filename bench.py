@@ -507,6 +507,23 @@ def bench_serve(args):
         finally:
             srv.close()
 
+    def run_alone():
+        """Each query on an idle server, one after another: its latency
+        with nothing else on the device."""
+        srv = api.Server(arena, slots=slots, query_workgroups=qwg, max_bypass=max_bypass, chunk_rows=chunk_rows)
+        try:
+            out = np.empty(Q)
+            for i in range(Q):
+                t0 = srv.clock()
+                srv.submit(specs[i])
+                comp = []
+                while not comp:
+                    comp, _, _ = srv.poll()
+                out[i] = comp[0][1] - t0
+            return out
+        finally:
+            srv.close()
+
     log("warm-up pass")
     run(np.zeros(Q))
     log("capacity: all queries at once")
@@ -516,6 +533,11 @@ def bench_serve(args):
     lat, span_o = run(np.cumsum(gaps) / rate)
     p50, p99 = np.percentile(lat, 50) * 1e3, np.percentile(lat, 99) * 1e3
     log(f"latency p50 {p50:.3f} ms, p99 {p99:.3f} ms, span {span_o * 1e3:.2f} ms")
+    alone = run_alone()
+    a50, a99 = np.percentile(alone, 50) * 1e3, np.percentile(alone, 99) * 1e3
+    slow = lat / alone
+    log(f"alone: p50 {a50:.3f} ms, p99 {a99:.3f} ms; in-mix/alone p50 {np.percentile(slow, 50):.2f}, "
+        f"p99 {np.percentile(slow, 99):.2f}")
     # plain FP64 atomic baseline: the same aggregates, one query after another
     outs = [torch.zeros(int(G), dtype=torch.float64, device=dev) for G in groups]
     prods = torch.empty(int(rows.max()), dtype=torch.float64, device=dev)
@@ -542,7 +564,12 @@ def bench_serve(args):
                    "queries": Q, "rows": n_all, "slots": slots, "max_bypass": max_bypass,
                    "query_workgroups": qwg, "chunk_rows": chunk_rows, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4), "mean": round(float(np.mean(lat)) * 1e3, 4),
-                       "offered_rate_qps": round(rate, 2), "open_loop_rows_per_s": n_all / span_o},
+                       "offered_rate_qps": round(rate, 2), "open_loop_rows_per_s": n_all / span_o,
+                       "alone_p50": round(a50, 4), "alone_p99": round(a99, 4),
+                       "in_mix_over_alone_p50": round(float(np.percentile(slow, 50)), 3),
+                       "in_mix_over_alone_p99": round(float(np.percentile(slow, 99)), 3),
+                       "note": "alone: each query on an idle server, one after another; in_mix_over_alone: "
+                               "per-query latency at the offered rate over its latency alone"},
         "step_hbm_frac": round(ach / HBM_PEAK_GBS, 4),
         "plain_fp64_atomic": {"ms_per_step": round(plain_s * 1e3, 4), "slowdown": round(span_c / plain_s, 3),
                               "note": "same aggregates, queries one after another"},
