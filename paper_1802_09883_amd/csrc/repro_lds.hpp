@@ -46,10 +46,18 @@ __global__ void __launch_bounds__(256) k_zero(unsigned long long* __restrict__ p
 // their common top J (the largest), moves each partial's levels down by its
 // distance to J and adds the level sums split as hi = sum(K >> CARRY),
 // lo = sum(K & (2^CARRY - 1)) (no int64 overflow: |K| < 2^62 per partial).
-// Level 2 (k_merge_l2): one lane per group adds the level-1 results and the
-// caller's state the same way and writes the canonical (S, C).
+// Level 2 (k_merge_l2): SL lanes per group (slices) add the level-1 results
+// and the caller's state the same way; the slice sums are folded in a tree
+// and the first slice writes the canonical (S, C).  The merge is bound by
+// the latency of its loads, so many slices (few partials per lane) pay.
 constexpr int M1_GROUPS = 64, M1_WAVES = 4;
-constexpr int M2_GROUPS = 16, M2_SLICES = 16;
+constexpr int M2_GROUPS = 16;
+// slices per group: the slice sums (SL x L x 16 groups x 2 words) stay
+// within the 64 KiB of static LDS
+template <int L>
+constexpr int m2_slices() {
+    return L <= 3 ? 64 : 32;
+}
 constexpr int64_t MERGE_DIRECT_MAX = 1 << 20;  // partials x groups merged by k_merge_l2 alone (one launch)
 constexpr int SEED_TILES = 64;      // tiles sampled for seed tops
 constexpr int SEED_MIN_TILES = 8;   // tiles per workgroup from which sampling pays
@@ -125,14 +133,14 @@ struct ColStates {
 // tops, qhi_ = their level sums K, split here as hi = K >> CARRY, lo = K &
 // (2^CARRY - 1); qlo_ unused): one launch merges few partials.  spill_ is
 // null when no workgroup could spill (one tile per workgroup).
-template <class AT, int L, bool RAW>
-__global__ void __launch_bounds__(M2_GROUPS* M2_SLICES)
+template <class AT, int L, bool RAW, int SL = m2_slices<L>()>
+__global__ void __launch_bounds__(M2_GROUPS* SL)
     k_merge_l2(const int* __restrict__ qtop_, const long long* __restrict__ qhi_, const long long* __restrict__ qlo_,
                int nq, int G, int gs, const unsigned long long* __restrict__ spill_, ColStates<AT> cs) {
     constexpr int NJ = Fmt<AT>::JMAX + 1;
     typedef Fmt<AT> F;
-    __shared__ int sJ[M2_SLICES][M2_GROUPS];
-    __shared__ long long sH[M2_SLICES][L][M2_GROUPS], sLo[M2_SLICES][L][M2_GROUPS];
+    __shared__ int sJ[SL][M2_GROUPS];
+    __shared__ long long sH[SL][L][M2_GROUPS], sLo[SL][L][M2_GROUPS];
     const int col = blockIdx.y;
     AT* __restrict__ S = cs.S[col];
     long long* __restrict__ C = cs.C[col];
@@ -146,16 +154,16 @@ __global__ void __launch_bounds__(M2_GROUPS* M2_SLICES)
     const int ts = state_top(S[gg]);
     int J = ts;
 #pragma unroll 4
-    for (int q = sl; q < nq; q += M2_SLICES) J = max(J, qtop[(size_t)q * gs + gg]);
+    for (int q = sl; q < nq; q += SL) J = max(J, qtop[(size_t)q * gs + gg]);
     sJ[sl][lane] = J;
     __syncthreads();
-#pragma unroll
-    for (int w = 0; w < M2_SLICES; ++w) J = max(J, sJ[w][lane]);
+#pragma unroll 8
+    for (int w = 0; w < SL; ++w) J = max(J, sJ[w][lane]);
     long long hi[L], lo[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) hi[l] = lo[l] = 0;
 #pragma unroll 4
-    for (int q = sl; q < nq; q += M2_SLICES) {
+    for (int q = sl; q < nq; q += SL) {
         const int d = J - qtop[(size_t)q * gs + gg];
         long long xh[L], xl[L];
 #pragma unroll
@@ -186,17 +194,26 @@ __global__ void __launch_bounds__(M2_GROUPS* M2_SLICES)
         sLo[sl][l][lane] = lo[l];
     }
     __syncthreads();
+    // tree over the slices (exact integer sums: the grouping changes no bit)
+#pragma unroll
+    for (int w = SL / 2; w > 0; w /= 2) {
+        if (sl < w) {
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                sH[sl][l][lane] += sH[sl + w][l][lane];
+                sLo[sl][l][lane] += sLo[sl + w][l][lane];
+            }
+        }
+        __syncthreads();
+    }
     if (sl != 0 || !gv) return;
     const int ds = J - ts;
 #pragma unroll
     for (int l = 0; l < L; ++l) {
         long long h = (l - ds >= 0) ? C[(size_t)(l - ds) * G + g] : 0;
         long long o = (l - ds >= 0) ? state_lo(S[(size_t)(l - ds) * G + g]) : 0;
-#pragma unroll
-        for (int w = 0; w < M2_SLICES; ++w) {
-            h += sH[w][l][lane];
-            o += sLo[w][l][lane];
-        }
+        h += sH[0][l][lane];
+        o += sLo[0][l][lane];
         if (spill_) {  // uniform
             // spilled units at lattice index J - l: H * 2^64 + w
             const unsigned long long* sw = spill_ + (((size_t)col * G + g) * NJ + (J - l)) * 2;
@@ -313,7 +330,7 @@ int run_merge(const Plan& p, int G, int nc, unsigned char* ws, const ColStates<A
         p.spill_used ? reinterpret_cast<const unsigned long long*>(ws + p.spill_off) : nullptr;
     const dim3 g2((G + M2_GROUPS - 1) / M2_GROUPS, nc);
     if ((int64_t)p.nwg * Gv <= MERGE_DIRECT_MAX) {  // few partial groups: one launch
-        hipLaunchKernelGGL((k_merge_l2<AT, L, true>), g2, dim3(M2_GROUPS * M2_SLICES), 0, st, ptop, pK, nullptr,
+        hipLaunchKernelGGL((k_merge_l2<AT, L, true>), g2, dim3(M2_GROUPS * m2_slices<L>()), 0, st, ptop, pK, nullptr,
                            p.nwg, G, Gv, spill, cs);
         LAUNCH_CHECK();
         return REPRO_OK;
@@ -321,7 +338,7 @@ int run_merge(const Plan& p, int G, int nc, unsigned char* ws, const ColStates<A
     hipLaunchKernelGGL((k_merge_l1<AT, L>), dim3((Gv + M1_GROUPS - 1) / M1_GROUPS, p.nq), dim3(M1_GROUPS * M1_WAVES),
                        0, st, ptop, pK, p.nwg, p.pb, Gv, qtop, qhi, qlo);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_merge_l2<AT, L, false>), g2, dim3(M2_GROUPS * M2_SLICES), 0, st, qtop, qhi, qlo, p.nq, G,
+    hipLaunchKernelGGL((k_merge_l2<AT, L, false>), g2, dim3(M2_GROUPS * m2_slices<L>()), 0, st, qtop, qhi, qlo, p.nq, G,
                        Gv, spill, cs);
     LAUNCH_CHECK();
     return REPRO_OK;
