@@ -241,3 +241,52 @@ def test_admission_bypass_with_aging(max_bypass):
     for s, keys, n in zip(specs, host, sizes):
         for o, r in zip(s.out, oracle_sums(pool, keys, 0, n, G)):
             assert np.array_equal(o.cpu().numpy(), r)
+
+
+def test_full_served_workload_sampled_against_oracle():
+    """The full served workload (128 queries, rows log-uniform 1e4..5e7,
+    groups 4..2^20, 4 aggregates over 6 decimal-like columns) in the launch
+    configuration the serving benchmark times (4 slots, bypass bound 8,
+    64M-row chunks, a 24 GiB arena, every query submitted at once).  The
+    oracle checks a seeded sample of the queries, the largest always among
+    them, bit for bit."""
+    import os
+    Q = 128
+    rows, groups, _ = WL.served_queries(Q)
+    n_max = int(rows.max())
+    pool = WL.decimal_columns(n_max, 6)
+    pool_t = [torch.from_numpy(np.ascontiguousarray(c)).cuda() for c in pool]
+    rng = np.random.default_rng(7)
+    offs = [int(rng.integers(0, n_max - int(n) + 1)) for n in rows]
+    say(f"case full served workload: {Q} queries, {int(rows.sum())} rows, largest {n_max}")
+    specs = []
+    for q, (n, G) in enumerate(zip(rows, groups)):
+        keys = torch.from_numpy(WL.served_keys(int(n), int(G), q)).cuda()
+        specs.append(api.QuerySpec(keys, [c[offs[q]:offs[q] + int(n)] for c in pool_t], int(G), WL.SERVED_AGGS, L=2))
+    srv = api.Server(24 << 30, slots=4, max_bypass=8, chunk_rows=64 << 20)
+    try:
+        for s in specs:
+            srv.submit(s)
+        done = set()
+        t0 = time.monotonic()
+        while len(done) < Q:
+            comp, _, _ = srv.poll()
+            done.update(t for t, _ in comp)
+            assert time.monotonic() - t0 < 60.0, "server did not finish"
+        torch.cuda.synchronize()
+    finally:
+        srv.close()
+    sample = sorted({int(np.argmax(rows))} | set(np.random.default_rng(11).choice(Q, 7, replace=False).tolist()))
+    threads = max(1, min(16, os.cpu_count() or 1))
+    for q in sample:
+        n, G = int(rows[q]), int(groups[q])
+        say(f"oracle: query {q}, {n} rows, {G} groups")
+        keys = WL.served_keys(n, G, q)
+        cols = [c[offs[q]:offs[q] + n] for c in pool]
+        for k, (a, b) in enumerate(WL.SERVED_AGGS):
+            v = cols[a] if b is None else cols[a] * cols[b]  # one IEEE rounding, as on the device
+            st, status = O.groupby_sum(keys, v, G, 2, True, threads=threads)
+            assert status == 0
+            ref = O.finalize(st, G, 2)
+            got = specs[q].out[k].cpu().numpy()
+            assert np.array_equal(got.view(np.uint8), ref.view(np.uint8)), f"query {q} aggregate {k} differs"
