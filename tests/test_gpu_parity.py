@@ -94,6 +94,21 @@ def test_lowcard_config_full():
         assert np.array_equal(out, O.finalize(orc, 1024, 3))
 
 
+def test_float_config_full():
+    """The float-accumulator workload at its full size: 200M f32 values
+    (exponents 2^U(-60,60), exact cancellation pairs) over 1024 groups into
+    repro<float,2>, in the launch the benchmark times."""
+    keys, _, v32 = WL.lowcard()
+    say("case float full: 2e8 rows, 1024 groups, repro<float,2>")
+    orc, ost = O.groupby_sum(keys, v32, 1024, 2, False, threads=16)
+    st, status = gpu_groupby(keys, v32, 1024, 2, False)
+    assert status == ost == 0
+    assert_same_states(st, orc, 1024, 2, False, "float full")
+    out = api.finalize(st, 1024, 2, TT(False)).cpu().numpy()
+    ref = O.finalize(orc, 1024, 2, False)
+    assert np.array_equal(out.view(np.uint8), ref.view(np.uint8))
+
+
 # ------------------------------------------------------- shapes, types
 
 @pytest.mark.parametrize("L", [1, 2, 3, 4])
