@@ -191,3 +191,27 @@ def test_query_bytes_without_gpu(lib):
         _lib.REPRO_EINVAL
     assert lib.repro_server_create(ctypes.c_void_p(257), 1 << 20, ctypes.byref(cfg), ctypes.byref(srv)) == \
         _lib.REPRO_EINVAL  # misaligned arena, rejected before any GPU call
+
+
+def test_server_poll_error_path_keeps_completions():
+    """The binding's poll on the library's error return: the completions the
+    call reported are kept in Server.completed and leave the live set, the
+    dropped query's ticket leaves it too, and the error names that ticket.
+    A stand-in library writes the outputs the C poll writes on that path."""
+    from paper_1802_09883_amd import api
+
+    class FakeLib:
+        def repro_server_poll(self, h, tk, tm, cap, nd, nq, nr, dr):
+            tk[0], tm[0], tk[1], tm[1] = 3, 1.5, 5, 2.5
+            nd._obj.value, nq._obj.value, nr._obj.value = 2, 1, 0
+            dr._obj.value = 7
+            return _lib.REPRO_EHIP
+
+    srv = object.__new__(api.Server)
+    srv.lib, srv.h = FakeLib(), None
+    srv.live = {3: "a", 5: "b", 7: "c", 9: "d"}
+    srv.completed = []
+    with pytest.raises(RuntimeError, match="dropped query 7"):
+        srv.poll(cap=4)
+    assert srv.completed == [(3, 1.5), (5, 2.5)]
+    assert set(srv.live) == {9}
