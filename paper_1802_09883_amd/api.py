@@ -418,7 +418,8 @@ def batch_tune(jobs, T=torch.float64, stream=None):
     # the largest workspace over the candidates the tuner times
     need = max(lib.repro_batch_workspace_bytes(arr, len(jobs), kt, vt, _T(T), _batch_config(
         {"chunk_rows": c, "max_slice_groups": cap, "merge": m, "split": sp}))
-               for c in (65536, 131072, 262144, 524288) for cap in (0, 1024) for m in (0, 1) for sp in (0, 1))
+               for c in (65536, 131072, 262144, 524288, 1048576, 2097152) for cap in (0, 1024) for m in (0, 1)
+               for sp in (0, 1))
     s = stream if stream is not None else torch.cuda.current_stream(dev)
     with torch.cuda.stream(s):
         ws = torch.empty(need, dtype=torch.uint8, device=dev)

@@ -794,7 +794,8 @@ int repro_batch_tune(const repro_batch_job* jobs, int njobs, repro_key_t kt, rep
                      void* workspace, size_t workspace_bytes, repro_batch_config* best, float* best_ms,
                      hipStream_t stream) {
     if (!best) return REPRO_EINVAL;
-    const int64_t chunks[] = {65536, 131072, 262144, 524288};
+    // chunk sizes: the binding sizes the workspace over these same candidates
+    const int64_t chunks[] = {65536, 131072, 262144, 524288, 1048576, 2097152};
     const int caps[] = {0, 1024};
     const int orders[] = {0, 1};
     const int merges[] = {0, 1};
